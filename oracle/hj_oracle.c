@@ -582,17 +582,25 @@ double hjo_certificate(const hjo_problem *P, const double *yN)
 /* A trial step counts as an ascent when it raises the objective by more than
  * a rounding allowance acc_rel * |Phi|; the allowance keeps rounding noise of
  * the objective from halving the step size near the optimum. */
-static int accept_step(double trial, double cur, double acc_rel)
+static int accept_step(const hjo_opts *O, double trial, double cur, double decrease)
 {
-    return trial <= cur + acc_rel * fabs(cur);
+    /* decrease = alpha * (directional derivative along the step), >= 0; the
+     * trial must realise the fraction armijo_c of it (Armijo's sufficient
+     * decrease; armijo_c = 0 is the plain "no ascent" test) */
+    return trial <= cur - O->armijo_c * decrease + O->acc_rel * fabs(cur);
+}
+
+/* max(s, a) that keeps a NaN once one has been seen */
+static double nan_max(double s, double a)
+{
+    return (a > s || a != a) ? a : s;
 }
 
 static double inf_norm(int n, const double *v)
 {
     double s = 0.0;
     for (int i = 0; i < n; ++i)
-        if (!(fabs(v[i]) <= s))
-            s = fabs(v[i]);
+        s = nan_max(s, fabs(v[i]));
     return s;
 }
 
@@ -609,14 +617,11 @@ int32_t hjo_descend(const hjo_problem *P, const hjo_opts *O, const double *x,
     int64_t fwd = 0, bwd = 0;
     double phi;
 
-    if (O->mode == HJO_GD) {
-        phi = hjo_grad_reverse(P, x, v, g, NULL);
-        hjo_eval(P, x, v, yN);
-        fwd += 1;
+    phi = hjo_eval(P, x, v, yN);
+    fwd += 1;
+    if (O->mode == HJO_GD && isfinite(phi)) {
+        hjo_grad_reverse(P, x, v, g, NULL);
         bwd += 1;
-    } else {
-        phi = hjo_eval(P, x, v, yN);
-        fwd += 1;
     }
     if (!isfinite(phi))
         status = HJO_ST_DIVERGED;
@@ -635,12 +640,11 @@ int32_t hjo_descend(const hjo_problem *P, const hjo_opts *O, const double *x,
                 double fm = hjo_eval(P, x, vt, NULL);
                 double gj = (fp - fm) / (2.0 * O->fd_sigma);
                 double step = alpha * gj;
-                if (!(fabs(step) <= smax))
-                    smax = fabs(step);
+                smax = nan_max(smax, fabs(step));
                 vt[j] = v[j] - step;
                 double ft = hjo_eval(P, x, vt, yNt);
                 fwd += 3;
-                if (accept_step(ft, phi, O->acc_rel)) {
+                if (accept_step(O, ft, phi, alpha * gj * gj)) {
                     v[j] = vt[j];
                     phi = ft;
                     memcpy(yN, yNt, sizeof(double) * 2 * n);
@@ -655,7 +659,7 @@ int32_t hjo_descend(const hjo_problem *P, const hjo_opts *O, const double *x,
                 vt[i] = v[i] - alpha * g[i];
             double ft = hjo_eval(P, x, vt, yNt);
             fwd += 1;
-            if (accept_step(ft, phi, O->acc_rel)) {
+            if (accept_step(O, ft, phi, alpha * dot(n, g, g))) {
                 memcpy(v, vt, sizeof(double) * n);
                 phi = ft;
                 memcpy(yN, yNt, sizeof(double) * 2 * n);

@@ -71,6 +71,7 @@ typedef struct {
     double  cert_tol;   /* certificate tolerance on rho                    */
     double  v_max;      /* divergence bound on |v|_inf                     */
     double  acc_rel;    /* relative rounding allowance of the ascent test  */
+    double  armijo_c;   /* required decrease fraction (0: plain ascent test) */
 } hjo_opts;
 
 /* Scalars m, m', m'' of the state-dependent speed as functions of r. */

@@ -39,7 +39,7 @@ class Opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_iter", C.c_int32), ("R_max", C.c_int32),
                 ("pad_", C.c_int32), ("alpha0", C.c_double), ("fd_sigma", C.c_double),
                 ("eps_step", C.c_double), ("cert_tol", C.c_double),
-                ("v_max", C.c_double), ("acc_rel", C.c_double)]
+                ("v_max", C.c_double), ("acc_rel", C.c_double), ("armijo_c", C.c_double)]
 
 
 class SlotDiag(C.Structure):
@@ -186,16 +186,16 @@ class Oracle:
     # -- descent and full solve ---------------------------------------------
     @staticmethod
     def opts(mode=1, max_iter=200, R_max=2, alpha0=0.1, fd_sigma=1e-4, eps_step=0.5e-7,
-             cert_tol=1e-8, v_max=1e6, acc_rel=64 * np.finfo(np.float64).eps):
+             cert_tol=1e-8, v_max=1e6, acc_rel=64 * np.finfo(np.float64).eps, armijo_c=0.0):
         return Opts(mode, max_iter, R_max, 0, alpha0, fd_sigma, eps_step, cert_tol,
-                    v_max, acc_rel)
+                    v_max, acc_rel, armijo_c)
 
     @staticmethod
     def opts_from_workload(wl, **over):
         kw = dict(mode=wl.mode, max_iter=wl.max_iter, R_max=wl.R_max, alpha0=wl.alpha0,
                   fd_sigma=wl.fd_sigma, eps_step=wl.eps_step, cert_tol=wl.cert_tol,
                   v_max=wl.v_max,
-                  acc_rel=wl.acc_rel)
+                  acc_rel=wl.acc_rel, armijo_c=wl.armijo_c)
         kw.update(over)
         return Oracle.opts(**kw)
 

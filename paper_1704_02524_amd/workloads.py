@@ -39,6 +39,11 @@ SEED_BASE = 170402524
 # paper's Lipschitz guess L = 3 of its smooth quadratic Example 2.
 ALPHA_DEFAULT = 1.0 / 3.0
 
+# The step is halved when a trial step fails to realise this fraction of the
+# decrease its gradient predicts (Armijo).  0 means halving on ascent only,
+# which the n=2 configuration states.
+ARMIJO_DEFAULT = 0.1
+
 
 @dataclasses.dataclass
 class Workload:
@@ -70,6 +75,7 @@ class Workload:
     ckpt_K: int = 16
     v_max: float = 1e6
     acc_rel: float = 64 * 2.220446049250313e-16
+    armijo_c: float = ARMIJO_DEFAULT
     cert_fp64: bool = True
     seed: int = 0
 
@@ -135,7 +141,7 @@ def c0_lax_n2(B: Optional[int] = None, seed: int = SEED_BASE + 0) -> Workload:
         kappa=0.25, s=1.0, w=0.0, d=np.ones(2), A=None, a=np.ones(2), j0=-0.5,
         formula=LAX, quad=TRAPZ, x=x[:B].copy(), guesses=guesses[:B].copy(),
         mode=CD_FD, dtype=F64, max_iter=100, alpha0=0.1, fd_sigma=1e-4,
-        eps_step=0.5e-7, cert_tol=1e-3, seed=seed)
+        eps_step=0.5e-7, cert_tol=1e-3, armijo_c=0.0, seed=seed)
 
 
 def c1_hopf_n10(B: int = 4096, seed: int = SEED_BASE + 1, mode: int = GD_ADJ) -> Workload:

@@ -501,6 +501,27 @@ def test_first_step_follows_the_exact_gradient(mode):
     assert r["n_bwd"] == (0 if mode == 0 else 2)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sufficient_decrease_rejects_overshoot(mode):
+    """n = 1 quadratic Hopf objective 1/2 lam v^2 - x v (lam = a^2 + t d): a
+    step with alpha lam = 1.9 lowers the objective by only 5% of alpha g^2, so
+    the plain ascent test accepts it while the sufficient-decrease test with
+    armijo_c = 0.1 rejects it and halves the step."""
+    a, t = 1.5, 0.4
+    lam = a * a + t
+    o = Oracle(n=1, t=t, nsteps=4, a=np.array([a]), j0=0.0, formula=HOPF, quad=RK4AUG)
+    x, v0 = np.array([0.7]), np.array([1.3])
+    g = lam * v0 - x
+    alpha = 1.9 / lam
+    for c, moved in [(0.0, True), (0.1, False)]:
+        r = o.descend(x, v0, Oracle.opts(mode=mode, max_iter=1, alpha0=alpha, eps_step=0.0,
+                                         R_max=0, armijo_c=c))
+        if moved:
+            np.testing.assert_allclose(r["v"], v0 - alpha * g, rtol=1e-9)
+        else:
+            np.testing.assert_array_equal(r["v"], v0)
+
+
 def test_uncertified_slot_reports_its_best_attempt():
     """With nothing certified, a slot reports the attempt with the lowest
     objective among its restarts."""
