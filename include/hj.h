@@ -1,0 +1,194 @@
+/*
+ * hj.h -- C interface of the MI355X (gfx950) solver for state-dependent
+ * Hamilton-Jacobi equations by the generalized Lax and Hopf formulas of
+ * Chow, Darbon, Osher and Yin (arXiv:1704.02524).
+ *
+ * Problem (paper section 2.1, eqs. HJeqn / HJinitial): find phi(x, t) with
+ *     phi_t + H(x, grad phi) = 0,   phi(x, 0) = g(x),
+ * for the Hamiltonian family
+ *     H(x, p) = <A x, p> + 1/2 m(|x|^2) sum_i d_i p_i^2 + 1/2 w |x|^2,
+ *     m = c^e,  c = 1 | 1 + kappa r/(1+r) | 1 + kappa tanh(r/s),  r = |x|^2,
+ * and ellipsoid initial data g(x) = 1/2 sum_i x_i^2 / a_i^2 + j0, whose
+ * conjugate is g*(p) = 1/2 sum_i a_i^2 p_i^2 - j0.
+ *
+ * Method (sections 3.3, 3.4, 4): for each query x and each initial guess v,
+ * integrate the bi-characteristics gamma' = H_p, p' = -H_x backward from
+ * gamma(t) = x, p(t) = v with classical RK4 on nsteps uniform steps, add the
+ * action integral by a quadrature rule, and minimise over v
+ *   Lax  (convex H):      F(v) = g(gamma(0)) + int_0^t <p, H_p> - H ds,
+ *                          phi = min F;
+ *   Hopf (convex g):      G(v) = g*(p(0)) + int_0^t H - <H_x, gamma> ds - <x, v>,
+ *                          phi = -min G;
+ * by cyclic coordinate descent with central differences (Algorithm 1 with
+ * step halving on ascent) or by gradient descent with the exact gradient of
+ * the discretised objective (a discrete adjoint with RK4 checkpoints).  The
+ * certificate of section 4.3 (Lax: p(0) = grad g(gamma(0)); Hopf, dual form:
+ * gamma(0) = grad g*(p(0))) accepts a result; a run that fails it restarts
+ * from the next guess (section 5: multiple random guesses).  The optimiser v
+ * is reported as argopt, the spatial gradient of phi where phi is smooth
+ * (section 1).
+ *
+ * Conventions for every entry point:
+ *  - Device arrays are caller-owned device pointers (hipMalloc'd or torch
+ *    tensors' data_ptr()), row-major and contiguous; "dtype" arrays hold
+ *    double for HJ_F64 and float for HJ_F32.
+ *  - Parameter arrays inside hj_h_params / hj_j_params are HOST pointers to
+ *    double and are copied during the call.
+ *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null stream)
+ *    and the call returns without waiting; results are valid once that stream
+ *    has completed.  Scratch memory comes from opts->workspace when it is
+ *    given (ws_bytes >= hj_workspace_size), else from an allocation the
+ *    library caches per device and grows as needed; calls that share that
+ *    cache must be ordered on one stream.
+ *  - Return value: HJ_OK (0) or a negative HJ_E* code; the message of the
+ *    last error on the calling thread is returned by hj_last_error().  No
+ *    entry point aborts the process.
+ */
+#ifndef HJ_H
+#define HJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HJ_VERSION 1
+
+/* return codes */
+#define HJ_OK            0
+#define HJ_EINVAL       -1  /* bad size, count or pointer                   */
+#define HJ_EDTYPE       -2  /* unknown dtype                                */
+#define HJ_ENOMEM       -3  /* workspace too small or allocation failed     */
+#define HJ_EDEVICE      -4  /* a HIP call failed                            */
+#define HJ_EUNSUPPORTED -5  /* valid but not built (e.g. n above the limit) */
+
+#define HJ_MAX_G    64      /* guesses per point                            */
+#define HJ_MAX_N   128      /* space dimension                              */
+
+enum { HJ_H_QUADRATIC = 0 };              /* H_kind: the family above       */
+enum { HJ_J_ELLIPSOID = 0 };              /* J_kind: ellipsoid g            */
+enum { HJ_M_CONST = 0, HJ_M_RAT = 1, HJ_M_TANH = 2 };
+enum { HJ_LAX = 0, HJ_HOPF = 1 };
+enum { HJ_TRAPZ = 0, HJ_RK4AUG = 1 };     /* trapezoid on the RK4 nodes, or
+                                             RK4 applied to a' = integrand */
+enum { HJ_CD_FD = 0, HJ_GD_ADJ = 1 };
+enum { HJ_F64 = 0, HJ_F32 = 1 };
+/* stop status of one descent run */
+enum { HJ_ST_MAXITER = 0, HJ_ST_CONVERGED = 1, HJ_ST_STALLED = 2, HJ_ST_DIVERGED = 3 };
+
+typedef struct {
+    int32_t m_kind;       /* HJ_M_*                                        */
+    int32_t e;            /* 1 or 2: m = c^e                               */
+    double  kappa;        /* amplitude of the state dependence of c        */
+    double  s;            /* tanh scale (HJ_M_TANH), > 0                   */
+    double  w;            /* potential 1/2 w |x|^2                         */
+    const double *d;      /* host [n] kinetic weights (usually +-1)        */
+    const double *A;      /* host [n*n] row-major drift, or NULL           */
+} hj_h_params;
+
+typedef struct {
+    const double *a;      /* host [n] ellipsoid semi-axes, nonzero         */
+    double j0;
+} hj_j_params;
+
+typedef struct {
+    int32_t G;            /* guesses (slots) per point, 1..HJ_MAX_G        */
+    int32_t R_max;        /* restarts per slot after the first attempt     */
+    const void *init;     /* device dtype [B, G, R_max+1, n]: attempt r of
+                             slot g at point b starts at init[b, g, r, :]  */
+} hj_guesses;
+
+typedef struct {
+    int32_t dtype;        /* HJ_F64 or HJ_F32: descent arithmetic          */
+    int32_t formula;      /* HJ_LAX or HJ_HOPF                             */
+    int32_t mode;         /* HJ_CD_FD or HJ_GD_ADJ                         */
+    int32_t quad;         /* HJ_TRAPZ or HJ_RK4AUG                         */
+    int32_t max_iter;     /* sweeps (CD_FD) or gradient steps (GD_ADJ)     */
+    int32_t ckpt_K;       /* adjoint checkpoint interval in steps (>= 1)   */
+    int32_t cert_fp64;    /* HJ_F32: re-evaluate objective and certificate
+                             in FP64 at each run's final v                 */
+    int32_t reserved;
+    double  alpha0;       /* initial step size (1/L of Algorithm 1)        */
+    double  fd_sigma;     /* central-difference step                       */
+    double  eps_step;     /* stop when an iteration's largest move < this  */
+    double  cert_tol;     /* certified iff residual <= cert_tol            */
+    double  v_max;        /* diverged when |v|_inf exceeds this            */
+    double  acc_rel;      /* rounding allowance of the step test (below)   */
+    double  armijo_c;     /* a trial step v' = v - alpha d is accepted iff
+                             F(v') <= F(v) - armijo_c alpha <g, d> + acc_rel |F(v)|
+                             with g the (FD or exact) gradient; else alpha
+                             is halved.  armijo_c = 0: halve on ascent.   */
+    void   *stream;       /* hipStream_t                                   */
+    void   *workspace;    /* optional device scratch                       */
+    size_t  ws_bytes;
+    void   *ev_begin;     /* optional hipEvent_t recorded on the stream just
+                             before the descent (or evaluation) kernel     */
+    void   *ev_end;       /* optional hipEvent_t recorded just after it    */
+} hj_opts;
+
+/* Optional per-slot outputs, device pointers, each NULL or [B, G] (v_final
+ * [B, G, n] in dtype).  A slot's reported attempt is its first certified
+ * one, else its finite attempt with the lowest objective. */
+typedef struct {
+    double  *phi;         /* objective of the reported attempt (FP64)      */
+    double  *rho;         /* its certificate residual (FP64)               */
+    int32_t *status;      /* its HJ_ST_* stop status                       */
+    int32_t *cert;        /* 1 certified, 0 finite uncertified, -1 none    */
+    int32_t *iters;       /* iterations over all attempts                  */
+    int32_t *attempts;    /* attempts used                                 */
+    int64_t *n_fwd;       /* forward solves over all attempts              */
+    int64_t *n_bwd;       /* adjoint sweeps over all attempts              */
+    void    *v_final;     /* the reported attempt's v                      */
+} hj_slot_diag;
+
+/* hj_solve -- phi(x_b, t) for B query points (sections 3.3-3.4, Algorithm 1,
+ * certificate of section 4.3, multiple guesses of section 5).
+ *   x          device dtype [B, n]
+ *   out_u      device double [B]: phi (Lax: min F; Hopf: -min G)
+ *   out_argopt device dtype [B, n]: the selected v (grad_x phi)
+ *   out_cert   device int32 [B]: 1 certified; 0 no slot certified, u and
+ *              argopt from the finite slot with the lowest objective;
+ *              -1 no finite slot (u = NaN)
+ *   diag       optional per-slot outputs (NULL for none)
+ * Selection: among certified slots the lowest objective, ties to the lowest
+ * slot index.  B = 0 is a no-op.  Errors: HJ_EINVAL for n < 1, nsteps < 1,
+ * t <= 0, G outside [1, HJ_MAX_G], R_max < 0, max_iter < 0, NULL arrays;
+ * HJ_EUNSUPPORTED for n > HJ_MAX_N or an unknown H_kind / J_kind. */
+int32_t hj_solve(int32_t H_kind, const hj_h_params *H, int32_t J_kind, const hj_j_params *J,
+                 const void *x, int64_t B, int32_t n, double t, int32_t nsteps,
+                 const hj_guesses *guesses, const hj_opts *opts,
+                 double *out_u, void *out_argopt, int32_t *out_cert,
+                 const hj_slot_diag *diag);
+
+/* hj_eval -- the discretised objective at given v (section 4.2) and,
+ * optionally, its exact gradient by the discrete adjoint of the RK4 solve
+ * and the quadrature.
+ *   x          device dtype [B, n];  v  device dtype [B, G, n]
+ *   out_phi    device double [B, G]: F (Lax) or G (Hopf)
+ *   out_yN     device dtype [B, G, 2n] or NULL: (gamma(0), p(0))
+ *   out_rho    device double [B, G] or NULL: certificate residual
+ *   out_grad_v device dtype [B, G, n] or NULL: d objective / d v
+ *   out_grad_x device dtype [B, G, n] or NULL: d objective / d x
+ * opts supplies dtype, formula, quad, ckpt_K, stream and workspace. */
+int32_t hj_eval(int32_t H_kind, const hj_h_params *H, int32_t J_kind, const hj_j_params *J,
+                const void *x, int64_t B, int32_t n, double t, int32_t nsteps,
+                const void *v, int32_t G, const hj_opts *opts,
+                double *out_phi, void *out_yN, double *out_rho,
+                void *out_grad_v, void *out_grad_x);
+
+/* Scratch bytes hj_solve / hj_eval need for B points of G slots. */
+size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps,
+                         const hj_opts *opts);
+
+/* Message of the last error on the calling thread ("" when none). */
+const char *hj_last_error(void);
+
+/* HJ_VERSION of the library. */
+int32_t hj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,474 @@
+// hj_api.hip -- host side of the C interface declared in include/hj.h:
+// argument checks, parameter staging, workspace layout, and the dispatch of
+// the templated kernels by (dtype, components per lane, lanes per task).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hj.h"
+#include "hj_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HJ_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(HJ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+// Library-owned scratch, one grow-only allocation per device.
+struct DevScratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+DevScratch g_ws[64];
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Vector layout: components per lane (NPL) and lanes per task (LPT) by n.
+struct Shape {
+  int npl, lpt;
+  int npad() const { return npl * lpt; }
+};
+
+bool pick_shape(int n, Shape& s) {
+  static const Shape table[] = {{2, 1}, {4, 1}, {8, 1}, {10, 1}, {8, 2},
+                                {8, 4}, {8, 8}, {13, 8}, {16, 8}};
+  for (const Shape& t : table)
+    if (n <= t.npad()) {
+      s = t;
+      return true;
+    }
+  return false;
+}
+
+// Layout of the scratch memory of one call.
+struct WsLayout {
+  size_t params = 0, slots = 0, ck = 0, seg = 0, total = 0;
+  size_t stride = 0;  // lanes of the SoA checkpoint arrays
+};
+
+WsLayout layout(int n, int64_t B, int G, int nsteps, int dtype, int mode, int K, bool grad,
+                bool solve) {
+  WsLayout L;
+  Shape s{};
+  pick_shape(n, s);
+  const size_t tsz = dtype == HJ_F32 ? 4 : 8;
+  const size_t BG = (size_t)B * (size_t)G;
+  size_t off = 0;
+  L.params = off;
+  off += align_up((size_t)s.npad() * 3 * (8 + tsz), 256);
+  if (solve) {
+    L.slots = off;
+    off += align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * (size_t)n * tsz, 256);
+  }
+  const bool need_adj = grad || (solve && mode == HJ_GD_ADJ);
+  if (need_adj) {
+    const size_t lanes = align_up(BG * (size_t)s.lpt, 256);
+    const int Kc = std::max(1, std::min(K, nsteps));
+    const size_t nck = (size_t)((nsteps + Kc - 1) / Kc) + 1;
+    L.stride = lanes;
+    L.ck = off;
+    off += align_up(nck * 2 * s.npl * lanes * tsz, 256);
+    L.seg = off;
+    off += align_up((size_t)Kc * 2 * s.npl * lanes * tsz, 256);
+  }
+  L.total = off;
+  return L;
+}
+
+int get_workspace(const hj_opts* o, size_t need, void** out) {
+  if (o && o->workspace) {
+    if (o->ws_bytes < need)
+      return fail(HJ_ENOMEM, "workspace of " + std::to_string(o->ws_bytes) +
+                                 " bytes is smaller than the " + std::to_string(need) +
+                                 " bytes needed");
+    *out = o->workspace;
+    return HJ_OK;
+  }
+  int dev = 0;
+  HJ_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HJ_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  DevScratch& w = g_ws[dev];
+  if (w.bytes < need) {
+    if (w.ptr) {
+      // the previous buffer may still be in use by queued work
+      HJ_HIP(hipDeviceSynchronize());
+      HJ_HIP(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    size_t bytes = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(&w.ptr, bytes) != hipSuccess) {
+      w.ptr = nullptr;
+      return fail(HJ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    w.bytes = bytes;
+  }
+  *out = w.ptr;
+  return HJ_OK;
+}
+
+int check_problem(int H_kind, const hj_h_params* H, int J_kind, const hj_j_params* J, int n,
+                  double t, int nsteps) {
+  if (H_kind != HJ_H_QUADRATIC) return fail(HJ_EUNSUPPORTED, "unknown H_kind");
+  if (J_kind != HJ_J_ELLIPSOID) return fail(HJ_EUNSUPPORTED, "unknown J_kind");
+  if (!H || !J) return fail(HJ_EINVAL, "H and J parameters are required");
+  if (n < 1) return fail(HJ_EINVAL, "n must be >= 1");
+  if (n > HJ_MAX_N) return fail(HJ_EUNSUPPORTED, "n above HJ_MAX_N");
+  if (!(t > 0.0) || !std::isfinite(t)) return fail(HJ_EINVAL, "t must be finite and > 0");
+  if (nsteps < 1) return fail(HJ_EINVAL, "nsteps must be >= 1");
+  if (H->m_kind < HJ_M_CONST || H->m_kind > HJ_M_TANH) return fail(HJ_EINVAL, "bad m_kind");
+  if (H->e != 1 && H->e != 2) return fail(HJ_EINVAL, "e must be 1 or 2");
+  if (H->m_kind == HJ_M_TANH && !(H->s > 0.0)) return fail(HJ_EINVAL, "tanh scale s must be > 0");
+  if (!H->d || !J->a) return fail(HJ_EINVAL, "d and a arrays are required");
+  if (H->A) return fail(HJ_EUNSUPPORTED, "the drift matrix A is not supported by this build");
+  for (int i = 0; i < n; ++i)
+    if (!(J->a[i] != 0.0) || !std::isfinite(J->a[i]))
+      return fail(HJ_EINVAL, "ellipsoid axes must be finite and nonzero");
+  return HJ_OK;
+}
+
+// Host copies of the per-component parameters, padded to npad.
+template <typename T> struct HostParams {
+  std::vector<T> d, a2, ia2;
+};
+template <typename T>
+HostParams<T> host_params(const hj_h_params* H, const hj_j_params* J, int n, int npad) {
+  HostParams<T> p;
+  p.d.assign(npad, T(0));
+  p.a2.assign(npad, T(1));
+  p.ia2.assign(npad, T(1));
+  for (int i = 0; i < n; ++i) {
+    const double a = J->a[i];
+    p.d[i] = (T)H->d[i];
+    p.a2[i] = (T)(a * a);
+    p.ia2[i] = (T)(1.0 / (a * a));
+  }
+  return p;
+}
+
+template <typename T>
+hj::Problem<T> make_problem(const hj_h_params* H, const hj_j_params* J, int n, double t,
+                            int nsteps, int formula, int quad, const T* dev) {
+  hj::Problem<T> P;
+  P.n = n;
+  P.N = nsteps;
+  P.m_kind = H->m_kind;
+  P.e = H->e;
+  P.formula = formula;
+  P.quad = quad;
+  P.kappa = (T)H->kappa;
+  P.inv_s = (T)(H->m_kind == HJ_M_TANH ? 1.0 / H->s : 1.0);
+  P.w = (T)H->w;
+  P.j0 = (T)J->j0;
+  P.h = (T)(t / nsteps);
+  return P;
+}
+
+// Stage d, a^2, 1/a^2 (in T and in double) into the params region.
+template <typename T>
+int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, char* region,
+                 hipStream_t st, const T** dT, const double** dD) {
+  HostParams<T> pt = host_params<T>(H, J, n, npad);
+  HostParams<double> pd = host_params<double>(H, J, n, npad);
+  std::vector<char> buf((size_t)npad * 3 * (sizeof(T) + 8));
+  char* q = buf.data();
+  std::memcpy(q, pt.d.data(), npad * sizeof(T));
+  std::memcpy(q + npad * sizeof(T), pt.a2.data(), npad * sizeof(T));
+  std::memcpy(q + 2 * npad * sizeof(T), pt.ia2.data(), npad * sizeof(T));
+  char* q2 = q + 3 * npad * sizeof(T);
+  std::memcpy(q2, pd.d.data(), npad * 8);
+  std::memcpy(q2 + npad * 8, pd.a2.data(), npad * 8);
+  std::memcpy(q2 + 2 * npad * 8, pd.ia2.data(), npad * 8);
+  // pageable source: the copy is staged before the call returns
+  HJ_HIP(hipMemcpyAsync(region, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
+  HJ_HIP(hipStreamSynchronize(st));
+  *dT = reinterpret_cast<const T*>(region);
+  *dD = reinterpret_cast<const double*>(region + 3 * npad * sizeof(T));
+  return HJ_OK;
+}
+
+template <typename T>
+void bind(hj::Problem<T>& P, const T* base, int npad) {
+  P.d = base;
+  P.a2 = base + npad;
+  P.ia2 = base + 2 * npad;
+}
+
+template <typename T, int NPL, int LPT>
+int launch_solve(const hj::SolveArgs<T>& A, int mode, hipStream_t st) {
+  const int64_t threads = A.B * A.G * LPT;
+  const int block = 256;
+  const int64_t grid = (threads + block - 1) / block;
+  if (mode == HJ_CD_FD)
+    hipLaunchKernelGGL((hj::k_solve_cd<T, NPL, LPT>), dim3((unsigned)grid), dim3(block), 0, st, A);
+  else
+    hipLaunchKernelGGL((hj::k_solve_gd<T, NPL, LPT>), dim3((unsigned)grid), dim3(block), 0, st, A);
+  HJ_HIP(hipGetLastError());
+  return HJ_OK;
+}
+
+template <typename T, int NPL, int LPT>
+int launch_eval(const hj::EvalArgs<T>& A, const hj_opts* o, hipStream_t st) {
+  const int64_t threads = A.B * A.G * LPT;
+  const int block = 256;
+  const int64_t grid = (threads + block - 1) / block;
+  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
+  hipLaunchKernelGGL((hj::k_eval<T, NPL, LPT>), dim3((unsigned)grid), dim3(block), 0, st, A);
+  HJ_HIP(hipGetLastError());
+  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
+  return HJ_OK;
+}
+
+// The descent kernel followed by the selection kernel.
+template <typename T, int NPL, int LPT>
+int launch_solve_then_select(const hj::SolveArgs<T>& A, const hj_opts* o, hipStream_t st,
+                             double* out_u, void* out_argopt, int32_t* out_cert) {
+  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
+  int rc = launch_solve<T, NPL, LPT>(A, o->mode, st);
+  if (rc) return rc;
+  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
+  const int block = 256;
+  const int64_t grid = (A.B + block - 1) / block;
+  hipLaunchKernelGGL((hj::k_select<T>), dim3((unsigned)grid), dim3(block), 0, st, A.B, A.G, A.P.n,
+                     A.P.formula, A.out.phi, A.out.cert, A.out.v, out_u,
+                     static_cast<T*>(out_argopt), out_cert);
+  HJ_HIP(hipGetLastError());
+  return HJ_OK;
+}
+
+#define HJ_DISPATCH(SHAPE, FN, ...)                                  \
+  switch (SHAPE.npl * 100 + SHAPE.lpt) {                             \
+    case 201: return FN<T, 2, 1>(__VA_ARGS__);                       \
+    case 401: return FN<T, 4, 1>(__VA_ARGS__);                       \
+    case 801: return FN<T, 8, 1>(__VA_ARGS__);                       \
+    case 1001: return FN<T, 10, 1>(__VA_ARGS__);                     \
+    case 802: return FN<T, 8, 2>(__VA_ARGS__);                       \
+    case 804: return FN<T, 8, 4>(__VA_ARGS__);                       \
+    case 808: return FN<T, 8, 8>(__VA_ARGS__);                       \
+    case 1308: return FN<T, 13, 8>(__VA_ARGS__);                     \
+    case 1608: return FN<T, 16, 8>(__VA_ARGS__);                     \
+    default: return fail(HJ_EUNSUPPORTED, "no kernel for this n");  \
+  }
+
+template <typename T>
+int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B, int n,
+            double t, int nsteps, const hj_guesses* gs, const hj_opts* o, double* out_u,
+            void* out_argopt, int32_t* out_cert, const hj_slot_diag* diag) {
+  Shape s{};
+  pick_shape(n, s);
+  const int npad = s.npad();
+  const int K = std::max(1, std::min(o->ckpt_K, nsteps));
+  WsLayout WL = layout(n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true);
+  void* ws = nullptr;
+  int rc = get_workspace(o, WL.total, &ws);
+  if (rc) return rc;
+  char* base = static_cast<char*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  const T* dT = nullptr;
+  const double* dD = nullptr;
+  rc = stage_params<T>(H, J, n, npad, base + WL.params, st, &dT, &dD);
+  if (rc) return rc;
+
+  hj::SolveArgs<T> A;
+  A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT);
+  bind(A.P, dT, npad);
+  A.P64 = make_problem<double>(H, J, n, t, nsteps, o->formula, o->quad, dD);
+  bind(A.P64, dD, npad);
+  A.x = static_cast<const T*>(x);
+  A.guesses = static_cast<const T*>(gs->init);
+  A.B = B;
+  A.G = gs->G;
+  A.R = gs->R_max;
+  A.max_iter = o->max_iter;
+  A.K = K;
+  A.cert_fp64 = o->cert_fp64;
+  A.alpha0 = (T)o->alpha0;
+  A.sigma = (T)o->fd_sigma;
+  A.eps_step = (T)o->eps_step;
+  A.acc_rel = (T)o->acc_rel;
+  A.armijo_c = (T)o->armijo_c;
+  A.v_max = (T)o->v_max;
+  A.cert_tol = o->cert_tol;
+  A.stride = WL.stride;
+  A.ck = WL.ck ? reinterpret_cast<T*>(base + WL.ck) : nullptr;
+  A.seg = WL.seg ? reinterpret_cast<T*>(base + WL.seg) : nullptr;
+  // per-slot records: caller's diag arrays where given, else scratch
+  const size_t BG = (size_t)B * gs->G;
+  char* sp = base + WL.slots;
+  double* w_phi = reinterpret_cast<double*>(sp);
+  double* w_rho = w_phi + BG;
+  int32_t* w_status = reinterpret_cast<int32_t*>(w_rho + BG);
+  int32_t* w_cert = w_status + BG;
+  int32_t* w_iters = w_cert + BG;
+  int32_t* w_att = w_iters + BG;
+  int64_t* w_fwd = reinterpret_cast<int64_t*>(w_att + BG);
+  int64_t* w_bwd = w_fwd + BG;
+  T* w_v = reinterpret_cast<T*>(sp + align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256));
+  A.out.phi = (diag && diag->phi) ? diag->phi : w_phi;
+  A.out.rho = (diag && diag->rho) ? diag->rho : w_rho;
+  A.out.status = (diag && diag->status) ? diag->status : w_status;
+  A.out.cert = (diag && diag->cert) ? diag->cert : w_cert;
+  A.out.iters = (diag && diag->iters) ? diag->iters : w_iters;
+  A.out.attempts = (diag && diag->attempts) ? diag->attempts : w_att;
+  A.out.n_fwd = (diag && diag->n_fwd) ? diag->n_fwd : w_fwd;
+  A.out.n_bwd = (diag && diag->n_bwd) ? diag->n_bwd : w_bwd;
+  A.out.v = (diag && diag->v_final) ? static_cast<T*>(diag->v_final) : w_v;
+
+  HJ_DISPATCH(s, launch_solve_then_select, A, o, st, out_u, out_argopt, out_cert);
+}
+
+template <typename T>
+int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B, int n,
+           double t, int nsteps, const void* v, int G, const hj_opts* o, double* out_phi,
+           void* out_yN, double* out_rho, void* out_gv, void* out_gx) {
+  Shape s{};
+  pick_shape(n, s);
+  const int npad = s.npad();
+  const int K = std::max(1, std::min(o->ckpt_K, nsteps));
+  const bool grad = out_gv || out_gx;
+  WsLayout WL = layout(n, B, G, nsteps, o->dtype, o->mode, K, grad, false);
+  void* ws = nullptr;
+  int rc = get_workspace(o, WL.total, &ws);
+  if (rc) return rc;
+  char* base = static_cast<char*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  const T* dT = nullptr;
+  const double* dD = nullptr;
+  rc = stage_params<T>(H, J, n, npad, base + WL.params, st, &dT, &dD);
+  if (rc) return rc;
+  hj::EvalArgs<T> A;
+  A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT);
+  bind(A.P, dT, npad);
+  A.x = static_cast<const T*>(x);
+  A.v = static_cast<const T*>(v);
+  A.B = B;
+  A.G = G;
+  A.K = K;
+  A.phi = out_phi;
+  A.rho = out_rho;
+  A.yN = static_cast<T*>(out_yN);
+  A.gv = static_cast<T*>(out_gv);
+  A.gx = static_cast<T*>(out_gx);
+  A.stride = WL.stride;
+  A.ck = grad ? reinterpret_cast<T*>(base + WL.ck) : nullptr;
+  A.seg = grad ? reinterpret_cast<T*>(base + WL.seg) : nullptr;
+  HJ_DISPATCH(s, launch_eval, A, o, st);
+}
+
+hj_opts default_opts() {
+  hj_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.dtype = HJ_F64;
+  o.formula = HJ_LAX;
+  o.mode = HJ_GD_ADJ;
+  o.quad = HJ_RK4AUG;
+  o.max_iter = 200;
+  o.ckpt_K = 16;
+  o.cert_fp64 = 1;
+  o.alpha0 = 1.0 / 3.0;
+  o.fd_sigma = 1e-4;
+  o.eps_step = 0.5e-7;
+  o.cert_tol = 1e-8;
+  o.v_max = 1e6;
+  o.acc_rel = 64 * 2.220446049250313e-16;
+  o.armijo_c = 0.1;
+  return o;
+}
+
+int check_opts(const hj_opts* o) {
+  if (o->dtype != HJ_F64 && o->dtype != HJ_F32) return fail(HJ_EDTYPE, "unknown dtype");
+  if (o->formula != HJ_LAX && o->formula != HJ_HOPF) return fail(HJ_EINVAL, "bad formula");
+  if (o->mode != HJ_CD_FD && o->mode != HJ_GD_ADJ) return fail(HJ_EINVAL, "bad mode");
+  if (o->quad != HJ_TRAPZ && o->quad != HJ_RK4AUG) return fail(HJ_EINVAL, "bad quadrature");
+  if (o->max_iter < 0) return fail(HJ_EINVAL, "max_iter must be >= 0");
+  if (o->ckpt_K < 1) return fail(HJ_EINVAL, "ckpt_K must be >= 1");
+  if (!(o->alpha0 > 0.0)) return fail(HJ_EINVAL, "alpha0 must be > 0");
+  if (!(o->armijo_c >= 0.0 && o->armijo_c < 1.0))
+    return fail(HJ_EINVAL, "armijo_c must be in [0, 1)");
+  if (o->mode == HJ_CD_FD && !(o->fd_sigma > 0.0)) return fail(HJ_EINVAL, "fd_sigma must be > 0");
+  return HJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hj_solve(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j_params* J,
+                 const void* x, int64_t B, int32_t n, double t, int32_t nsteps,
+                 const hj_guesses* guesses, const hj_opts* opts, double* out_u,
+                 void* out_argopt, int32_t* out_cert, const hj_slot_diag* diag) {
+  g_last_error.clear();
+  int rc = check_problem(H_kind, H, J_kind, J, n, t, nsteps);
+  if (rc) return rc;
+  if (B < 0) return fail(HJ_EINVAL, "B must be >= 0");
+  if (!guesses) return fail(HJ_EINVAL, "guesses are required");
+  if (guesses->G < 1 || guesses->G > HJ_MAX_G) return fail(HJ_EINVAL, "G must be in [1, 64]");
+  if (guesses->R_max < 0) return fail(HJ_EINVAL, "R_max must be >= 0");
+  hj_opts o = opts ? *opts : default_opts();
+  rc = check_opts(&o);
+  if (rc) return rc;
+  if (B == 0) return HJ_OK;
+  if (!x || !guesses->init || !out_u || !out_argopt || !out_cert)
+    return fail(HJ_EINVAL, "x, guesses->init and the outputs are required");
+  if (B * (int64_t)guesses->G * 16 > (int64_t)UINT32_MAX * 256 / 2)
+    return fail(HJ_EINVAL, "B * G too large for one launch");
+  if (o.dtype == HJ_F64)
+    return solve_t<double>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert,
+                           diag);
+  return solve_t<float>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert, diag);
+}
+
+int32_t hj_eval(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j_params* J,
+                const void* x, int64_t B, int32_t n, double t, int32_t nsteps, const void* v,
+                int32_t G, const hj_opts* opts, double* out_phi, void* out_yN, double* out_rho,
+                void* out_grad_v, void* out_grad_x) {
+  g_last_error.clear();
+  int rc = check_problem(H_kind, H, J_kind, J, n, t, nsteps);
+  if (rc) return rc;
+  if (B < 0) return fail(HJ_EINVAL, "B must be >= 0");
+  if (G < 1 || G > HJ_MAX_G) return fail(HJ_EINVAL, "G must be in [1, 64]");
+  hj_opts o = opts ? *opts : default_opts();
+  rc = check_opts(&o);
+  if (rc) return rc;
+  if (B == 0) return HJ_OK;
+  if (!x || !v || !out_phi) return fail(HJ_EINVAL, "x, v and out_phi are required");
+  if (o.dtype == HJ_F64)
+    return eval_t<double>(H, J, x, B, n, t, nsteps, v, G, &o, out_phi, out_yN, out_rho,
+                          out_grad_v, out_grad_x);
+  return eval_t<float>(H, J, x, B, n, t, nsteps, v, G, &o, out_phi, out_yN, out_rho, out_grad_v,
+                       out_grad_x);
+}
+
+size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const hj_opts* opts) {
+  if (n < 1 || n > HJ_MAX_N || B < 0 || G < 1 || nsteps < 1) return 0;
+  hj_opts o = opts ? *opts : default_opts();
+  const int K = std::max(1, std::min(o.ckpt_K, nsteps));
+  // the larger of what hj_solve and hj_eval (with gradients) need
+  WsLayout a = layout(n, B, G, nsteps, o.dtype, o.mode, K, false, true);
+  WsLayout b = layout(n, B, G, nsteps, o.dtype, o.mode, K, true, false);
+  return std::max(a.total, b.total);
+}
+
+const char* hj_last_error(void) { return g_last_error.c_str(); }
+
+int32_t hj_version(void) { return HJ_VERSION; }
+
+}  // extern "C"

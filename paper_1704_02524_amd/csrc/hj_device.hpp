@@ -1,0 +1,568 @@
+// hj_device.hpp -- device-side building blocks of the Lax / Hopf solver for
+// gfx950: the Hamiltonian family, the RK4 characteristic solve with the
+// action quadrature, the discrete adjoint, and wave-level reductions.
+//
+// Layout: one "task" is one (query point, guess slot).  A task is held by LPT
+// adjacent lanes of a wavefront; lane `sub` of the group owns the NPL vector
+// components sub*NPL .. sub*NPL+NPL-1 of gamma, p, v, ... in registers
+// (padding components carry d = 0, x = v = 0 and stay exactly zero).  Sums
+// over components are butterfly reductions inside the group, so every lane of
+// a group holds bit-identical scalars and takes identical branches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hj.h"
+
+namespace hj {
+
+// ---------------------------------------------------------------------------
+// math helpers
+// ---------------------------------------------------------------------------
+// expm1(y) for y <= 0 in FP64: Cody-Waite reduction y = k ln2 + f with
+// |f| <= ln2/2 (ln2 split into a 32-bit head and a tail), Taylor polynomial
+// of expm1(f) to degree 13 (truncation below 1e-17 relative), and
+// expm1(y) = 2^k expm1(f) + (2^k - 1).  Relative error a few ulp.
+__device__ __forceinline__ double expm1_neg(double y) {
+  const double ln2_hi = 6.93147180369123816490e-01;  // head of ln 2 (exact in 32 bits)
+  const double ln2_lo = 1.90821492927058770002e-10;  // ln 2 - ln2_hi
+  const double inv_ln2 = 1.44269504088896338700e+00;
+  const double k = __builtin_rint(y * inv_ln2);
+  double f = __builtin_fma(-k, ln2_hi, y);
+  f = __builtin_fma(-k, ln2_lo, f);
+  // f + f^2/2! + ... + f^13/13!  (Horner on the coefficients 1/j!)
+  double p = 1.0 / 6227020800.0;                 // 1/13!
+  p = __builtin_fma(p, f, 1.0 / 479001600.0);    // 1/12!
+  p = __builtin_fma(p, f, 1.0 / 39916800.0);     // 1/11!
+  p = __builtin_fma(p, f, 1.0 / 3628800.0);      // 1/10!
+  p = __builtin_fma(p, f, 1.0 / 362880.0);       // 1/9!
+  p = __builtin_fma(p, f, 1.0 / 40320.0);        // 1/8!
+  p = __builtin_fma(p, f, 1.0 / 5040.0);         // 1/7!
+  p = __builtin_fma(p, f, 1.0 / 720.0);          // 1/6!
+  p = __builtin_fma(p, f, 1.0 / 120.0);          // 1/5!
+  p = __builtin_fma(p, f, 1.0 / 24.0);           // 1/4!
+  p = __builtin_fma(p, f, 1.0 / 6.0);            // 1/3!
+  p = __builtin_fma(p, f, 0.5);                  // 1/2!
+  p = __builtin_fma(p * f, f, f);                // f + f^2 (1/2 + ...)
+  const double s = __builtin_ldexp(1.0, (int)k); // exact; 0 for very negative k
+  return __builtin_fma(s, p, s - 1.0);
+}
+
+// tanh in FP64 from expm1: tanh|z| = -e / (2 + e), e = expm1(-2|z|); exact
+// limit 1 for |z| > 20 (tanh(20) = 1 - 8e-18).
+__device__ __forceinline__ double dtanh(double z) {
+  const double az = __builtin_fabs(z);
+  double t = 1.0;
+  if (az <= 20.0) {
+    const double e = expm1_neg(-2.0 * az);
+    t = -e / (2.0 + e);
+  }
+  if (z != z) t = z;
+  return __builtin_copysign(t, z);
+}
+__device__ __forceinline__ float dtanh(float x) { return tanhf(x); }
+__device__ __forceinline__ double dabs(double x) { return fabs(x); }
+__device__ __forceinline__ float dabs(float x) { return fabsf(x); }
+template <typename T> __device__ __forceinline__ bool finite_(T x) { return isfinite(x); }
+
+// Max that propagates NaN: once NaN, stays NaN.
+template <typename T> __device__ __forceinline__ T nanmax(T s, T a) {
+  return (a > s || a != a) ? a : s;
+}
+
+// Butterfly sum / max over the LPT lanes of a task group.  Addition is
+// commutative, so all lanes of the group end with the same bits.
+template <int LPT, typename T> __device__ __forceinline__ T gsum(T v) {
+#pragma unroll
+  for (int o = LPT / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, LPT);
+  return v;
+}
+template <int LPT, typename T> __device__ __forceinline__ T gmax(T v) {
+#pragma unroll
+  for (int o = LPT / 2; o >= 1; o >>= 1) v = nanmax(v, __shfl_xor(v, o, LPT));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// problem description, in the arithmetic type T
+// ---------------------------------------------------------------------------
+template <typename T> struct Problem {
+  int n;        // true dimension
+  int N;        // RK4 steps
+  int m_kind;   // HJ_M_*
+  int e;        // 1 or 2
+  int formula;  // HJ_LAX / HJ_HOPF
+  int quad;     // HJ_TRAPZ / HJ_RK4AUG
+  T kappa, inv_s, w, j0, h;
+  const T* d;    // [npad] kinetic weights, 0 in padding
+  const T* a2;   // [npad] a_i^2, 1 in padding
+  const T* ia2;  // [npad] 1 / a_i^2, 1 in padding
+};
+
+// Per-lane copy of the component parameters (uniform across the wave when
+// LPT == 1, so the compiler keeps them in scalar registers).
+template <typename T, int NPL> struct LaneParams {
+  T d[NPL], a2[NPL], ia2[NPL];
+  __device__ __forceinline__ void load(const Problem<T>& P, int sub) {
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      d[k] = P.d[sub * NPL + k];
+      a2[k] = P.a2[sub * NPL + k];
+      ia2[k] = P.ia2[sub * NPL + k];
+    }
+  }
+};
+
+// m = c^e and its derivatives in r = |gamma|^2.
+template <typename T, bool NEED2>
+__device__ __forceinline__ void speed(const Problem<T>& P, T r, T& m, T& m1, T& m2) {
+  T c, c1, c2 = T(0);
+  if (P.m_kind == HJ_M_TANH) {
+    const T th = dtanh(r * P.inv_s);
+    const T sech2 = T(1) - th * th;
+    c = T(1) + P.kappa * th;
+    c1 = P.kappa * P.inv_s * sech2;
+    if (NEED2) c2 = T(-2) * P.kappa * P.inv_s * P.inv_s * th * sech2;
+  } else if (P.m_kind == HJ_M_RAT) {
+    const T q = T(1) / (T(1) + r);
+    c = T(1) + P.kappa * r * q;
+    c1 = P.kappa * q * q;
+    if (NEED2) c2 = T(-2) * P.kappa * q * q * q;
+  } else {
+    c = T(1);
+    c1 = T(0);
+  }
+  if (P.e == 2) {
+    m = c * c;
+    m1 = T(2) * c * c1;
+    m2 = NEED2 ? T(2) * c1 * c1 + T(2) * c * c2 : T(0);
+  } else {
+    m = c;
+    m1 = c1;
+    m2 = c2;
+  }
+}
+
+// Integrand of the action at a state with scalars (r, q, m, m1):
+//   Lax  <p, H_p> - H       = 1/2 m q - 1/2 w r
+//   Hopf H - <H_x, gamma>   = 1/2 m q - q m' r - 1/2 w r
+template <typename T>
+__device__ __forceinline__ T integrand(const Problem<T>& P, T r, T q, T m, T m1) {
+  T v = T(0.5) * m * q - T(0.5) * P.w * r;
+  if (P.formula == HJ_HOPF) v -= q * m1 * r;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// RK4 in reversed time: y' = f(y), f(gamma, p) = (-m D p, (q m' + w) gamma)
+// (no drift).  NT independent trajectories are advanced together so their
+// instruction streams interleave.
+// ---------------------------------------------------------------------------
+template <typename T, int NPL, int LPT, int NT> struct Traj {
+  T g[NT][NPL], p[NT][NPL];
+};
+
+// r = |gamma|^2 and q = sum d p^2 at the stage state (G, Pp) for NT trajectories.
+template <typename T, int NPL, int LPT, int NT>
+__device__ __forceinline__ void reduce_rq(const T (&G)[NT][NPL], const T (&Pp)[NT][NPL],
+                                          const LaneParams<T, NPL>& L, T (&r)[NT], T (&q)[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T rr = T(0), qq = T(0);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      rr += G[t][k] * G[t][k];
+      qq += L.d[k] * Pp[t][k] * Pp[t][k];
+    }
+    r[t] = rr;
+    q[t] = qq;
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    r[t] = gsum<LPT>(r[t]);
+    q[t] = gsum<LPT>(q[t]);
+  }
+}
+
+// One RK4 step y -> y_next for NT trajectories.  With QUAD the RK4-augmented
+// quadrature of the integrand is added into acc.  The y update is the same
+// instruction sequence with or without QUAD, which keeps the adjoint's
+// recomputation bit-identical to the forward solve.
+template <typename T, int NPL, int LPT, int NT, bool QUAD>
+__device__ __forceinline__ void rk4_step(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                         T (&g)[NT][NPL], T (&p)[NT][NPL], T (&acc)[NT]) {
+  const T h = P.h, h2 = T(0.5) * P.h, h6 = P.h / T(6), h3 = P.h / T(3);
+  T G[NT][NPL], Pp[NT][NPL], ag[NT][NPL], ap[NT][NPL];
+  T r[NT], q[NT], m[NT], m1[NT], m2[NT], ia[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    ia[t] = T(0);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      G[t][k] = g[t][k];
+      Pp[t][k] = p[t][k];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    reduce_rq<T, NPL, LPT, NT>(G, Pp, L, r, q);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) speed<T, false>(P, r[t], m[t], m1[t], m2[t]);
+    const T wb = (s == 0 || s == 3) ? h6 : h3;  // RK4 weights h/6 (1, 2, 2, 1)
+    const T cn = (s == 2) ? h : h2;             // next stage offset c_{s+1} h
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (QUAD) ia[t] += (s == 0 || s == 3 ? T(1) : T(2)) * integrand(P, r[t], q[t], m[t], m1[t]);
+      const T cx = q[t] * m1[t] + P.w;
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        const T kg = -m[t] * (L.d[k] * Pp[t][k]);
+        const T kp = cx * G[t][k];
+        if (s == 0) {
+          ag[t][k] = g[t][k] + wb * kg;
+          ap[t][k] = p[t][k] + wb * kp;
+        } else {
+          ag[t][k] = ag[t][k] + wb * kg;
+          ap[t][k] = ap[t][k] + wb * kp;
+        }
+        if (s < 3) {
+          G[t][k] = g[t][k] + cn * kg;
+          Pp[t][k] = p[t][k] + cn * kp;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (QUAD) acc[t] += h6 * ia[t];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      g[t][k] = ag[t][k];
+      p[t][k] = ap[t][k];
+    }
+  }
+}
+
+// Integrand at a node (trapezoid rule).
+template <typename T, int NPL, int LPT, int NT>
+__device__ __forceinline__ void node_integrand(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                               const T (&g)[NT][NPL], const T (&p)[NT][NPL],
+                                               T (&out)[NT]) {
+  T r[NT], q[NT];
+  reduce_rq<T, NPL, LPT, NT>(g, p, L, r, q);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T m, m1, m2;
+    speed<T, false>(P, r[t], m, m1, m2);
+    out[t] = integrand(P, r[t], q[t], m, m1);
+  }
+}
+
+// Checkpoint storage: structure-of-arrays, lane-contiguous.  Slot c of
+// component k of a lane lives at base[(c * 2 * NPL + k) * stride + lane].
+template <typename T, int NPL>
+__device__ __forceinline__ void store_state(T* base, size_t stride, size_t lane, int c,
+                                            const T (&g)[NPL], const T (&p)[NPL]) {
+  T* b = base + (size_t)c * 2 * NPL * stride + lane;
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    b[(size_t)k * stride] = g[k];
+    b[(size_t)(NPL + k) * stride] = p[k];
+  }
+}
+template <typename T, int NPL>
+__device__ __forceinline__ void load_state(const T* base, size_t stride, size_t lane, int c,
+                                           T (&g)[NPL], T (&p)[NPL]) {
+  const T* b = base + (size_t)c * 2 * NPL * stride + lane;
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    g[k] = b[(size_t)k * stride];
+    p[k] = b[(size_t)(NPL + k) * stride];
+  }
+}
+
+// Objective (paper section 4.1 functionals F and G, discretised) for NT
+// trajectories started at (x, v[t]); also the certificate residual rho and,
+// with STORE, the states y_{cK} (c = 0 .. ceil(N/K)-1) and y_N (slot
+// ceil(N/K)) for the adjoint of trajectory 0.
+template <typename T, int NPL, int LPT, int NT, bool STORE>
+__device__ __forceinline__ void forward(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                        const T (&x)[NPL], const T (&v)[NT][NPL], T (&phi)[NT],
+                                        T (&rho)[NT], T* ck = nullptr, size_t stride = 0,
+                                        size_t lane = 0, int K = 1,
+                                        T (*yN_g)[NPL] = nullptr, T (*yN_p)[NPL] = nullptr) {
+  T g[NT][NPL], p[NT][NPL], acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = T(0);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      g[t][k] = x[k];
+      p[t][k] = v[t][k];
+    }
+  }
+  const bool aug = (P.quad == HJ_RK4AUG);
+  if (!aug) {
+    T io[NT];
+    node_integrand<T, NPL, LPT, NT>(P, L, g, p, io);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] += T(0.5) * P.h * io[t];
+  }
+  for (int s = 0; s < P.N; ++s) {
+    if (STORE && (s % K) == 0) store_state<T, NPL>(ck, stride, lane, s / K, g[0], p[0]);
+    if (aug) {
+      rk4_step<T, NPL, LPT, NT, true>(P, L, g, p, acc);
+    } else {
+      rk4_step<T, NPL, LPT, NT, false>(P, L, g, p, acc);
+      T io[NT];
+      node_integrand<T, NPL, LPT, NT>(P, L, g, p, io);
+      const T wk = (s + 1 < P.N) ? P.h : T(0.5) * P.h;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] += wk * io[t];
+    }
+  }
+  if (STORE) store_state<T, NPL>(ck, stride, lane, (P.N + K - 1) / K, g[0], p[0]);
+  // terminal term, residual
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T term = T(0), res = T(0);
+    if (P.formula == HJ_LAX) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        term += g[t][k] * g[t][k] * L.ia2[k];
+        res = nanmax(res, dabs(p[t][k] - g[t][k] * L.ia2[k]));
+      }
+      term = T(0.5) * gsum<LPT>(term) + P.j0;
+    } else {
+      T xv = T(0);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        term += L.a2[k] * p[t][k] * p[t][k];
+        xv += x[k] * v[t][k];
+        res = nanmax(res, dabs(g[t][k] - L.a2[k] * p[t][k]));
+      }
+      term = T(0.5) * gsum<LPT>(term) - P.j0 - gsum<LPT>(xv);
+    }
+    phi[t] = term + acc[t];
+    rho[t] = gmax<LPT>(res);
+    if (yN_g) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        yN_g[t][k] = g[t][k];
+        yN_p[t][k] = p[t][k];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint (exact gradient of the discretised objective).
+// ---------------------------------------------------------------------------
+
+// Scalars of one stage state.
+template <typename T> struct StageScal {
+  T r, q, m, m1, m2;
+};
+
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ StageScal<T> stage_scalars(const Problem<T>& P,
+                                                      const LaneParams<T, NPL>& L,
+                                                      const T (&G)[NPL], const T (&Pp)[NPL]) {
+  StageScal<T> S;
+  T rr = T(0), qq = T(0);
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    rr += G[k] * G[k];
+    qq += L.d[k] * Pp[k] * Pp[k];
+  }
+  S.r = gsum<LPT>(rr);
+  S.q = gsum<LPT>(qq);
+  speed<T, true>(P, S.r, S.m, S.m1, S.m2);
+  return S;
+}
+
+// Coefficients of the integrand gradient: grad_gamma = cg gamma,
+// grad_p = cp D p.
+template <typename T>
+__device__ __forceinline__ void integrand_grad_coef(const Problem<T>& P, const StageScal<T>& S,
+                                                    T& cg, T& cp) {
+  if (P.formula == HJ_LAX) {
+    cg = S.q * S.m1 - P.w;
+    cp = S.m;
+  } else {
+    cg = -(S.q * (S.m1 + T(2) * S.r * S.m2) + P.w);
+    cp = S.m - T(2) * S.r * S.m1;
+  }
+}
+
+// Vector-Jacobian product of f at a stage state, plus wb * grad(integrand):
+//   out_gamma = -2 m' <D p, kg> gamma + 2 q m'' <gamma, kp> gamma
+//               + (q m' + w) kp + wb cg gamma
+//   out_p     = D (-m kg + 2 m' <gamma, kp> p + wb cp p)
+// (kg, kp) is read from and out is written to the same arrays.
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ void vjp_stage(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                          const T (&G)[NPL], const T (&Pp)[NPL],
+                                          const StageScal<T>& S, T wb, T (&kg)[NPL],
+                                          T (&kp)[NPL]) {
+  T s1 = T(0), s2 = T(0);
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    s1 += L.d[k] * Pp[k] * kg[k];
+    s2 += G[k] * kp[k];
+  }
+  s1 = gsum<LPT>(s1);
+  s2 = gsum<LPT>(s2);
+  T cg = T(0), cp = T(0);
+  if (wb != T(0)) integrand_grad_coef(P, S, cg, cp);
+  const T ag = T(-2) * S.m1 * s1 + T(2) * S.q * S.m2 * s2 + wb * cg;
+  const T al = S.q * S.m1 + P.w;
+  const T ap = T(2) * S.m1 * s2 + wb * cp;
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    const T og = ag * G[k] + al * kp[k];
+    const T op = L.d[k] * (-S.m * kg[k] + ap * Pp[k]);
+    kg[k] = og;
+    kp[k] = op;
+  }
+}
+
+// Reverse sweep through one RK4 step from y_k = (g, p): lam holds d(obj)/d
+// y_{k+1} on entry and d(obj)/d y_k on exit (stage recomputation in registers).
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ void reverse_step(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                             const T (&g)[NPL], const T (&p)[NPL], bool aug,
+                                             T (&lg)[NPL], T (&lp)[NPL]) {
+  const T h = P.h, h2 = T(0.5) * P.h, h6 = P.h / T(6), h3 = P.h / T(3);
+  T YG[4][NPL], YP[4][NPL];
+  StageScal<T> S[4];
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    YG[0][k] = g[k];
+    YP[0][k] = p[k];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    S[s] = stage_scalars<T, NPL, LPT>(P, L, YG[s], YP[s]);
+    if (s < 3) {
+      const T cn = (s == 2) ? h : h2;
+      const T cx = S[s].q * S[s].m1 + P.w;
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        const T kg = -S[s].m * (L.d[k] * YP[s][k]);
+        const T kp = cx * YG[s][k];
+        YG[s + 1][k] = g[k] + cn * kg;
+        YP[s + 1][k] = p[k] + cn * kp;
+      }
+    }
+  }
+  // ybar accumulates d/dy_k; bg/bp carries Ybar of the stage above.
+  T yg[NPL], yp[NPL], bg[NPL], bp[NPL];
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    yg[k] = lg[k];
+    yp[k] = lp[k];
+  }
+#pragma unroll
+  for (int s = 3; s >= 0; --s) {
+    const T wb = (s == 0 || s == 3) ? h6 : h3;
+    const T cn = (s == 2) ? h : h2;  // c_{s+1} h: offset of stage s+1 on K_s
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      if (s == 3) {
+        bg[k] = wb * lg[k];
+        bp[k] = wb * lp[k];
+      } else {
+        bg[k] = wb * lg[k] + cn * bg[k];
+        bp[k] = wb * lp[k] + cn * bp[k];
+      }
+    }
+    vjp_stage<T, NPL, LPT>(P, L, YG[s], YP[s], S[s], aug ? wb : T(0), bg, bp);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      yg[k] += bg[k];
+      yp[k] += bp[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    lg[k] = yg[k];
+    lp[k] = yp[k];
+  }
+}
+
+// lam += wk * grad(integrand)(y)   (trapezoid node term)
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ void add_node_grad(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                              const T (&g)[NPL], const T (&p)[NPL], T wk,
+                                              T (&lg)[NPL], T (&lp)[NPL]) {
+  const StageScal<T> S = stage_scalars<T, NPL, LPT>(P, L, g, p);
+  T cg, cp;
+  integrand_grad_coef(P, S, cg, cp);
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    lg[k] += wk * cg * g[k];
+    lp[k] += wk * cp * L.d[k] * p[k];
+  }
+}
+
+// Gradient of the objective w.r.t. (x, v) from the checkpoints written by
+// forward<STORE>.  seg is per-lane scratch for K states.
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ void backward(const Problem<T>& P, const LaneParams<T, NPL>& L,
+                                         const T (&x)[NPL], const T (&v)[NPL], const T* ck,
+                                         T* seg, size_t stride, size_t lane, int K,
+                                         T (&gv)[NPL], T (&gx)[NPL]) {
+  const bool aug = (P.quad == HJ_RK4AUG);
+  const int nseg = (P.N + K - 1) / K;
+  T lg[NPL], lp[NPL], g[NPL], p[NPL];
+  load_state<T, NPL>(ck, stride, lane, nseg, g, p);  // y_N
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    if (P.formula == HJ_LAX) {
+      lg[k] = g[k] * L.ia2[k];
+      lp[k] = T(0);
+    } else {
+      lg[k] = T(0);
+      lp[k] = L.a2[k] * p[k];
+    }
+  }
+  if (!aug) add_node_grad<T, NPL, LPT>(P, L, g, p, T(0.5) * P.h, lg, lp);
+  for (int c = nseg - 1; c >= 0; --c) {
+    const int k0 = c * K;
+    const int k1 = (k0 + K < P.N) ? k0 + K : P.N;
+    load_state<T, NPL>(ck, stride, lane, c, g, p);
+    // recompute y_{k0+1} .. y_{k1-1} with the forward's own step function
+    for (int j = k0 + 1; j < k1; ++j) {
+      T gg[1][NPL], pp[1][NPL], dummy[1] = {T(0)};
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        gg[0][k] = g[k];
+        pp[0][k] = p[k];
+      }
+      rk4_step<T, NPL, LPT, 1, false>(P, L, gg, pp, dummy);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        g[k] = gg[0][k];
+        p[k] = pp[0][k];
+      }
+      store_state<T, NPL>(seg, stride, lane, j - k0, g, p);
+    }
+    for (int j = k1 - 1; j >= k0; --j) {
+      if (j == k0)
+        load_state<T, NPL>(ck, stride, lane, c, g, p);
+      else
+        load_state<T, NPL>(seg, stride, lane, j - k0, g, p);
+      reverse_step<T, NPL, LPT>(P, L, g, p, aug, lg, lp);
+      if (!aug) add_node_grad<T, NPL, LPT>(P, L, g, p, j == 0 ? T(0.5) * P.h : P.h, lg, lp);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    gv[k] = lp[k] - (P.formula == HJ_HOPF ? x[k] : T(0));
+    gx[k] = lg[k] - (P.formula == HJ_HOPF ? v[k] : T(0));
+  }
+}
+
+}  // namespace hj

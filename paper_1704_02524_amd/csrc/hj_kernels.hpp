@@ -1,0 +1,414 @@
+// hj_kernels.hpp -- the solver kernels: objective evaluation (with optional
+// exact gradient), central-difference coordinate descent, adjoint gradient
+// descent, and per-point selection over the guess slots.
+#pragma once
+
+#include "hj_device.hpp"
+
+namespace hj {
+
+// Per-slot result records (device arrays [B*G], v in [B*G, n]).
+template <typename T> struct SlotOut {
+  double* phi;
+  double* rho;
+  int32_t* status;
+  int32_t* cert;
+  int32_t* iters;
+  int32_t* attempts;
+  int64_t* n_fwd;
+  int64_t* n_bwd;
+  T* v;
+};
+
+template <typename T> struct SolveArgs {
+  Problem<T> P;
+  Problem<double> P64;  // the same problem in FP64 (certificate of FP32 runs)
+  const T* x;           // [B, n]
+  const T* guesses;     // [B, G, R+1, n]
+  int64_t B;
+  int G, R;
+  int max_iter, K;
+  int cert_fp64;
+  T alpha0, sigma, eps_step, acc_rel, armijo_c, v_max;
+  double cert_tol;
+  T* ck;                // adjoint checkpoints, SoA over `stride` lanes
+  T* seg;               // adjoint segment scratch
+  size_t stride;
+  SlotOut<T> out;
+};
+
+template <typename T> struct EvalArgs {
+  Problem<T> P;
+  const T* x;   // [B, n]
+  const T* v;   // [B, G, n]
+  int64_t B;
+  int G, K;
+  double* phi;  // [B, G]
+  double* rho;  // [B, G] or null
+  T* yN;        // [B, G, 2n] or null
+  T* gv;        // [B, G, n] or null
+  T* gx;        // [B, G, n] or null
+  T* ck;
+  T* seg;
+  size_t stride;
+};
+
+// load n-vector row `row` into the lane's NPL components (0 beyond n)
+template <typename T, int NPL>
+__device__ __forceinline__ void load_row(const T* base, int n, int sub, T (&out)[NPL]) {
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    const int i = sub * NPL + k;
+    out[k] = (i < n) ? base[i] : T(0);
+  }
+}
+template <typename T, int NPL>
+__device__ __forceinline__ void store_row(T* base, int n, int sub, const T (&in)[NPL]) {
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    const int i = sub * NPL + k;
+    if (i < n) base[i] = in[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// objective evaluation (and exact gradient)
+// ---------------------------------------------------------------------------
+template <typename T, int NPL, int LPT>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs<T> A) {
+  const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x % LPT;
+  const int64_t task = (int64_t)(lane / LPT);
+  if (task >= A.B * A.G) return;
+  const int64_t b = task / A.G;
+  const int n = A.P.n;
+  LaneParams<T, NPL> L;
+  L.load(A.P, sub);
+  T x[NPL], v[1][NPL], phi[1], rho[1], yg[1][NPL], yp[1][NPL];
+  load_row<T, NPL>(A.x + b * n, n, sub, x);
+  load_row<T, NPL>(A.v + task * n, n, sub, v[0]);
+  const bool grad = (A.gv != nullptr) || (A.gx != nullptr);
+  if (grad)
+    forward<T, NPL, LPT, 1, true>(A.P, L, x, v, phi, rho, A.ck, A.stride, lane, A.K, yg, yp);
+  else
+    forward<T, NPL, LPT, 1, false>(A.P, L, x, v, phi, rho, nullptr, 0, 0, 1, yg, yp);
+  if (sub == 0) {
+    A.phi[task] = (double)phi[0];
+    if (A.rho) A.rho[task] = (double)rho[0];
+  }
+  if (A.yN) {
+    store_row<T, NPL>(A.yN + task * 2 * n, n, sub, yg[0]);
+    store_row<T, NPL>(A.yN + task * 2 * n + n, n, sub, yp[0]);
+  }
+  if (grad) {
+    T gv[NPL], gx[NPL];
+    backward<T, NPL, LPT>(A.P, L, x, v[0], A.ck, A.seg, A.stride, lane, A.K, gv, gx);
+    if (A.gv) store_row<T, NPL>(A.gv + task * n, n, sub, gv);
+    if (A.gx) store_row<T, NPL>(A.gx + task * n, n, sub, gx);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// shared per-slot bookkeeping
+// ---------------------------------------------------------------------------
+template <typename T> struct SlotBest {
+  double phi = __builtin_nan(""), rho = __builtin_nan("");
+  int32_t cert = -1, status = HJ_ST_DIVERGED, iters = 0, attempts = 0;
+  int64_t n_fwd = 0, n_bwd = 0;
+};
+
+// Certificate and objective of a finished run, in FP64.  FP32 runs with the
+// FP64 certificate re-solve the characteristic in FP64 at the final v.
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ void final_values(const SolveArgs<T>& A, int sub, const T (&x)[NPL],
+                                             const T (&v)[NPL], T phi, T rho, double& phi64,
+                                             double& rho64) {
+  if (sizeof(T) == 4 && A.cert_fp64) {
+    LaneParams<double, NPL> L64;
+    L64.load(A.P64, sub);
+    double x64[NPL], v64[1][NPL], ph[1], rh[1];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      x64[k] = (double)x[k];
+      v64[0][k] = (double)v[k];
+    }
+    forward<double, NPL, LPT, 1, false>(A.P64, L64, x64, v64, ph, rh);
+    phi64 = ph[0];
+    rho64 = rh[0];
+  } else {
+    phi64 = (double)phi;
+    rho64 = (double)rho;
+  }
+}
+
+// Record the end of one attempt; returns true when the slot is finished.
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ bool end_attempt(const SolveArgs<T>& A, int sub, int64_t task,
+                                            const T (&x)[NPL], const T (&v)[NPL], T phi, T rho,
+                                            int status, int it, int att, SlotBest<T>& best) {
+  double phi64, rho64;
+  if (status == HJ_ST_DIVERGED) {
+    phi64 = (double)phi;
+    rho64 = __builtin_nan("");
+  } else {
+    final_values<T, NPL, LPT>(A, sub, x, v, phi, rho, phi64, rho64);
+  }
+  best.iters += it;
+  best.attempts = att + 1;
+  const bool fin = (status != HJ_ST_DIVERGED) && isfinite(phi64);
+  const bool certified = fin && (rho64 <= A.cert_tol);
+  if (certified || (fin && (best.cert < 0 || phi64 < best.phi))) {
+    best.phi = phi64;
+    best.rho = rho64;
+    best.cert = certified ? 1 : 0;
+    best.status = status;
+    store_row<T, NPL>(A.out.v + task * A.P.n, A.P.n, sub, v);
+  }
+  return certified || (att + 1 > A.R);
+}
+
+template <typename T, int NPL, int LPT>
+__device__ __forceinline__ void write_slot(const SolveArgs<T>& A, int sub, int64_t task,
+                                           const SlotBest<T>& best) {
+  if (best.cert < 0) {
+    T nanv[NPL];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) nanv[k] = T(__builtin_nan(""));
+    store_row<T, NPL>(A.out.v + task * A.P.n, A.P.n, sub, nanv);
+  }
+  if (sub != 0) return;
+  if (A.out.phi) A.out.phi[task] = best.phi;
+  if (A.out.rho) A.out.rho[task] = best.rho;
+  if (A.out.status) A.out.status[task] = best.status;
+  if (A.out.cert) A.out.cert[task] = best.cert;
+  if (A.out.iters) A.out.iters[task] = best.iters;
+  if (A.out.attempts) A.out.attempts[task] = best.attempts;
+  if (A.out.n_fwd) A.out.n_fwd[task] = best.n_fwd;
+  if (A.out.n_bwd) A.out.n_bwd[task] = best.n_bwd;
+}
+
+// Step test: the trial must realise the fraction armijo_c of the decrease
+// alpha <g, d> its gradient predicts, up to a rounding allowance acc_rel |F|
+// (armijo_c = 0: no ascent).
+template <typename T>
+__device__ __forceinline__ bool accept_step(const SolveArgs<T>& A, T trial, T cur, T decrease) {
+  return trial <= cur - A.armijo_c * decrease + A.acc_rel * dabs(cur);
+}
+
+// ---------------------------------------------------------------------------
+// cyclic coordinate descent with central differences (Algorithm 1; one
+// iteration = one sweep over the n coordinates; the step halves on ascent)
+// ---------------------------------------------------------------------------
+template <typename T, int NPL, int LPT>
+__global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<T> A) {
+  const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x % LPT;
+  const int64_t task = (int64_t)(lane / LPT);
+  if (task >= A.B * A.G) return;
+  const int64_t b = task / A.G;
+  const int n = A.P.n;
+  LaneParams<T, NPL> L;
+  L.load(A.P, sub);
+  T x[NPL], v[NPL];
+  load_row<T, NPL>(A.x + b * n, n, sub, x);
+  const T* g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
+  load_row<T, NPL>(g0, n, sub, v);
+  SlotBest<T> best;
+  const T alpha_floor = A.alpha0 * T(9.094947017729282e-13);  // alpha0 * 2^-40
+  int att = 0, it = 0, j = 0;
+  bool start = true;
+  T alpha = A.alpha0, phi = T(0), rho = T(0), smax = T(0);
+  while (true) {
+    // pair: the two central-difference points (or the start point)
+    T va[2][NPL], fp[2], rp[2];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      const bool on = !start && (sub * NPL + k == j);
+      va[0][k] = on ? v[k] + A.sigma : v[k];
+      va[1][k] = on ? v[k] - A.sigma : v[k];
+    }
+    forward<T, NPL, LPT, 2, false>(A.P, L, x, va, fp, rp);
+    int status = -1;
+    if (start) {
+      best.n_fwd += 1;
+      phi = fp[0];
+      rho = rp[0];
+      start = false;
+      it = 0;
+      j = 0;
+      smax = T(0);
+      alpha = A.alpha0;
+      if (!isfinite(phi))
+        status = HJ_ST_DIVERGED;
+      else if (A.max_iter == 0)
+        status = HJ_ST_MAXITER;
+    } else {
+      const T gj = (fp[0] - fp[1]) / (T(2) * A.sigma);
+      const T step = alpha * gj;
+      smax = nanmax(smax, dabs(step));
+      T vt[1][NPL], ft[1], rt[1];
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) vt[0][k] = (sub * NPL + k == j) ? v[k] - step : v[k];
+      forward<T, NPL, LPT, 1, false>(A.P, L, x, vt, ft, rt);
+      best.n_fwd += 3;
+      if (accept_step(A, ft[0], phi, alpha * gj * gj)) {
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) v[k] = vt[0][k];
+        phi = ft[0];
+        rho = rt[0];
+      } else {
+        alpha *= T(0.5);
+      }
+      if (++j == n) {
+        j = 0;
+        ++it;
+        T vmax = T(0);
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
+        vmax = gmax<LPT>(vmax);
+        if (!isfinite(phi) || !(vmax <= A.v_max))
+          status = HJ_ST_DIVERGED;
+        else if (smax < A.eps_step)
+          status = HJ_ST_CONVERGED;
+        else if (alpha < alpha_floor)
+          status = HJ_ST_STALLED;
+        else if (it >= A.max_iter)
+          status = HJ_ST_MAXITER;
+        smax = T(0);
+      }
+    }
+    if (status >= 0) {
+      if (end_attempt<T, NPL, LPT>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
+      ++att;
+      load_row<T, NPL>(g0 + (int64_t)att * n, n, sub, v);
+      start = true;
+    }
+  }
+  write_slot<T, NPL, LPT>(A, sub, task, best);
+}
+
+// ---------------------------------------------------------------------------
+// gradient descent with the exact discrete gradient (adjoint + checkpoints)
+// ---------------------------------------------------------------------------
+template <typename T, int NPL, int LPT>
+__global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<T> A) {
+  const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x % LPT;
+  const int64_t task = (int64_t)(lane / LPT);
+  if (task >= A.B * A.G) return;
+  const int64_t b = task / A.G;
+  const int n = A.P.n;
+  LaneParams<T, NPL> L;
+  L.load(A.P, sub);
+  T x[NPL], v[NPL], g[NPL];
+  load_row<T, NPL>(A.x + b * n, n, sub, x);
+  const T* g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
+  load_row<T, NPL>(g0, n, sub, v);
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) g[k] = T(0);
+  SlotBest<T> best;
+  const T alpha_floor = A.alpha0 * T(9.094947017729282e-13);  // alpha0 * 2^-40
+  int att = 0, it = 0;
+  bool start = true;
+  T alpha = A.alpha0, phi = T(0), rho = T(0);
+  while (true) {
+    // trial point
+    T vt[1][NPL], ft[1], rt[1], smax = T(0), gg = T(0);
+    if (start) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) vt[0][k] = v[k];
+    } else {
+      T gm = T(0);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        gm = nanmax(gm, dabs(g[k]));
+        gg += g[k] * g[k];
+        vt[0][k] = v[k] - alpha * g[k];
+      }
+      smax = alpha * gmax<LPT>(gm);
+      gg = gsum<LPT>(gg);
+    }
+    forward<T, NPL, LPT, 1, true>(A.P, L, x, vt, ft, rt, A.ck, A.stride, lane, A.K);
+    best.n_fwd += 1;
+    const bool acc = start || accept_step(A, ft[0], phi, alpha * gg);
+    if (acc) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) v[k] = vt[0][k];
+      phi = ft[0];
+      rho = rt[0];
+    } else {
+      alpha *= T(0.5);
+    }
+    if (acc && isfinite(phi)) {
+      T gx[NPL];
+      backward<T, NPL, LPT>(A.P, L, x, v, A.ck, A.seg, A.stride, lane, A.K, g, gx);
+      best.n_bwd += 1;
+    }
+    int status = -1;
+    if (start) {
+      start = false;
+      it = 0;
+      alpha = A.alpha0;
+      if (!isfinite(phi))
+        status = HJ_ST_DIVERGED;
+      else if (A.max_iter == 0)
+        status = HJ_ST_MAXITER;
+    } else {
+      ++it;
+      T vmax = T(0);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
+      vmax = gmax<LPT>(vmax);
+      if (!isfinite(phi) || !(vmax <= A.v_max))
+        status = HJ_ST_DIVERGED;
+      else if (smax < A.eps_step)
+        status = HJ_ST_CONVERGED;
+      else if (alpha < alpha_floor)
+        status = HJ_ST_STALLED;
+      else if (it >= A.max_iter)
+        status = HJ_ST_MAXITER;
+    }
+    if (status >= 0) {
+      if (end_attempt<T, NPL, LPT>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
+      ++att;
+      load_row<T, NPL>(g0 + (int64_t)att * n, n, sub, v);
+      start = true;
+    }
+  }
+  write_slot<T, NPL, LPT>(A, sub, task, best);
+}
+
+// ---------------------------------------------------------------------------
+// selection over the G slots of each point (certified first, lowest
+// objective, ties to the lowest slot)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_select(int64_t B, int G, int n, int formula,
+                                                const double* s_phi, const int32_t* s_cert,
+                                                const T* s_v, double* out_u, T* out_arg,
+                                                int32_t* out_cert) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  int pick = -1, pc = -1;
+  double best = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const int c = s_cert[b * G + g];
+    if (c < 0) continue;
+    const double ph = s_phi[b * G + g];
+    if (c > pc || (c == pc && ph < best)) {
+      pick = g;
+      pc = c;
+      best = ph;
+    }
+  }
+  out_cert[b] = pc;
+  if (pick < 0) {
+    out_u[b] = __builtin_nan("");
+    for (int i = 0; i < n; ++i) out_arg[b * n + i] = T(__builtin_nan(""));
+  } else {
+    out_u[b] = (formula == HJ_LAX) ? best : -best;
+    for (int i = 0; i < n; ++i) out_arg[b * n + i] = s_v[(b * G + pick) * n + i];
+  }
+}
+
+}  // namespace hj

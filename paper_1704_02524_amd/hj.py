@@ -1,0 +1,245 @@
+"""Python binding of the C interface in include/hj.h (argument marshalling
+only: every step of the solve runs in the HIP kernels of libhj.so).
+
+Device arrays are torch tensors on a ROCm device; PyTorch provides device
+memory and streams.  The library must have been built (``python -m
+paper_1704_02524_amd.build``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhj.so")
+
+HJ_OK, HJ_EINVAL, HJ_EDTYPE, HJ_ENOMEM, HJ_EDEVICE, HJ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+HJ_H_QUADRATIC, HJ_J_ELLIPSOID = 0, 0
+ST_MAXITER, ST_CONVERGED, ST_STALLED, ST_DIVERGED = 0, 1, 2, 3
+
+_dp = C.POINTER(C.c_double)
+
+
+class HParams(C.Structure):
+    _fields_ = [("m_kind", C.c_int32), ("e", C.c_int32), ("kappa", C.c_double),
+                ("s", C.c_double), ("w", C.c_double), ("d", _dp), ("A", _dp)]
+
+
+class JParams(C.Structure):
+    _fields_ = [("a", _dp), ("j0", C.c_double)]
+
+
+class Guesses(C.Structure):
+    _fields_ = [("G", C.c_int32), ("R_max", C.c_int32), ("init", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("formula", C.c_int32), ("mode", C.c_int32),
+                ("quad", C.c_int32), ("max_iter", C.c_int32), ("ckpt_K", C.c_int32),
+                ("cert_fp64", C.c_int32), ("reserved", C.c_int32),
+                ("alpha0", C.c_double), ("fd_sigma", C.c_double), ("eps_step", C.c_double),
+                ("cert_tol", C.c_double), ("v_max", C.c_double), ("acc_rel", C.c_double),
+                ("armijo_c", C.c_double),
+                ("stream", C.c_void_p), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
+
+
+class SlotDiag(C.Structure):
+    _fields_ = [("phi", C.c_void_p), ("rho", C.c_void_p), ("status", C.c_void_p),
+                ("cert", C.c_void_p), ("iters", C.c_void_p), ("attempts", C.c_void_p),
+                ("n_fwd", C.c_void_p), ("n_bwd", C.c_void_p), ("v_final", C.c_void_p)]
+
+
+class HJError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhj.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HJError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1704_02524_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.hj_solve.restype = C.c_int32
+        L.hj_solve.argtypes = [C.c_int32, C.POINTER(HParams), C.c_int32, C.POINTER(JParams),
+                               C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
+                               C.POINTER(Guesses), C.POINTER(Opts), C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.POINTER(SlotDiag)]
+        L.hj_eval.restype = C.c_int32
+        L.hj_eval.argtypes = [C.c_int32, C.POINTER(HParams), C.c_int32, C.POINTER(JParams),
+                              C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
+                              C.c_void_p, C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p]
+        L.hj_workspace_size.restype = C.c_size_t
+        L.hj_workspace_size.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                        C.POINTER(Opts)]
+        L.hj_last_error.restype = C.c_char_p
+        L.hj_last_error.argtypes = []
+        L.hj_version.restype = C.c_int32
+        L.hj_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != HJ_OK:
+        raise HJError(f"libhj error {rc}: {lib().hj_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _tdtype(dtype: int):
+    return torch.float64 if dtype == W.F64 else torch.float32
+
+
+class Problem:
+    """Host-side H and J parameters of a workload, kept alive for the call."""
+
+    def __init__(self, wl):
+        import numpy as np
+        self.n = wl.n
+        self._d = np.ascontiguousarray(wl.d, dtype=np.float64)
+        self._a = np.ascontiguousarray(wl.a, dtype=np.float64)
+        self._A = None if wl.A is None else np.ascontiguousarray(wl.A, dtype=np.float64)
+        self.H = HParams(wl.m_kind, wl.e, wl.kappa, wl.s, wl.w,
+                         self._d.ctypes.data_as(_dp),
+                         None if self._A is None else self._A.ctypes.data_as(_dp))
+        self.J = JParams(self._a.ctypes.data_as(_dp), wl.j0)
+
+
+def make_opts(wl, stream: Optional[torch.cuda.Stream] = None, events=None, **over) -> Opts:
+    """hj_opts from a workload; `events` = (begin, end) torch.cuda.Event pair
+    recorded by the library around its descent / evaluation kernel."""
+    kw = dict(dtype=wl.dtype, formula=wl.formula, mode=wl.mode, quad=wl.quad,
+              max_iter=wl.max_iter, ckpt_K=wl.ckpt_K, cert_fp64=int(wl.cert_fp64),
+              alpha0=wl.alpha0, fd_sigma=wl.fd_sigma, eps_step=wl.eps_step,
+              cert_tol=wl.cert_tol, v_max=wl.v_max, acc_rel=wl.acc_rel,
+              armijo_c=wl.armijo_c)
+    kw.update(over)
+    o = Opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    o.stream = C.c_void_p(s.cuda_stream)
+    if events is not None:
+        o.ev_begin = C.c_void_p(events[0].cuda_event)
+        o.ev_end = C.c_void_p(events[1].cuda_event)
+    return o
+
+
+def device_inputs(wl, device="cuda"):
+    """x [B, n] and guesses [B, G, R+1, n] as device tensors of the run dtype."""
+    dt = _tdtype(wl.dtype)
+    x = torch.as_tensor(wl.x, dtype=dt).to(device).contiguous()
+    g = torch.as_tensor(wl.guesses, dtype=dt).to(device).contiguous()
+    return x, g
+
+
+def solve(wl, x: torch.Tensor, guesses: torch.Tensor, diag: bool = True,
+          stream: Optional[torch.cuda.Stream] = None, out=None, events=None, **opt_over):
+    """hj_solve on device tensors x [B, n], guesses [B, G, R+1, n].
+
+    Returns a dict of device tensors: u [B] (float64), argopt [B, n],
+    cert [B] (int32) and, with diag, the per-slot records."""
+    B, n = x.shape
+    G, R1 = guesses.shape[1], guesses.shape[2]
+    dev = x.device
+    dt = _tdtype(wl.dtype)
+    assert x.dtype == dt and guesses.dtype == dt
+    assert x.is_contiguous() and guesses.is_contiguous()
+    assert guesses.shape == (B, G, R1, n)
+    prob = Problem(wl)
+    o = make_opts(wl, stream, events, **opt_over)
+    if out is None:
+        out = dict(u=torch.empty(B, dtype=torch.float64, device=dev),
+                   argopt=torch.empty(B, n, dtype=dt, device=dev),
+                   cert=torch.empty(B, dtype=torch.int32, device=dev))
+        if diag:
+            out.update(
+                slot_phi=torch.empty(B, G, dtype=torch.float64, device=dev),
+                slot_rho=torch.empty(B, G, dtype=torch.float64, device=dev),
+                slot_status=torch.empty(B, G, dtype=torch.int32, device=dev),
+                slot_cert=torch.empty(B, G, dtype=torch.int32, device=dev),
+                slot_iters=torch.empty(B, G, dtype=torch.int32, device=dev),
+                slot_attempts=torch.empty(B, G, dtype=torch.int32, device=dev),
+                slot_fwd=torch.empty(B, G, dtype=torch.int64, device=dev),
+                slot_bwd=torch.empty(B, G, dtype=torch.int64, device=dev),
+                slot_v=torch.empty(B, G, n, dtype=dt, device=dev))
+    D = None
+    if "slot_phi" in out:
+        D = SlotDiag(_ptr(out["slot_phi"]), _ptr(out["slot_rho"]), _ptr(out["slot_status"]),
+                     _ptr(out["slot_cert"]), _ptr(out["slot_iters"]),
+                     _ptr(out["slot_attempts"]), _ptr(out["slot_fwd"]), _ptr(out["slot_bwd"]),
+                     _ptr(out["slot_v"]))
+    gs = Guesses(G, R1 - 1, _ptr(guesses))
+    rc = lib().hj_solve(HJ_H_QUADRATIC, C.byref(prob.H), HJ_J_ELLIPSOID, C.byref(prob.J),
+                        _ptr(x), B, n, float(wl.t), int(wl.nsteps), C.byref(gs), C.byref(o),
+                        _ptr(out["u"]), _ptr(out["argopt"]), _ptr(out["cert"]),
+                        C.byref(D) if D is not None else None)
+    _check(rc)
+    return out
+
+
+def evaluate(wl, x: torch.Tensor, v: torch.Tensor, grad: bool = False, yN: bool = False,
+             stream: Optional[torch.cuda.Stream] = None, **opt_over):
+    """hj_eval: objective (and certificate residual, end state, exact
+    gradients) at v [B, G, n] for the queries x [B, n]."""
+    B, n = x.shape
+    G = v.shape[1]
+    dev = x.device
+    dt = _tdtype(wl.dtype)
+    assert x.dtype == dt and v.dtype == dt and v.shape == (B, G, n)
+    assert x.is_contiguous() and v.is_contiguous()
+    prob = Problem(wl)
+    o = make_opts(wl, stream, **opt_over)
+    out = dict(phi=torch.empty(B, G, dtype=torch.float64, device=dev),
+               rho=torch.empty(B, G, dtype=torch.float64, device=dev))
+    if yN:
+        out["yN"] = torch.empty(B, G, 2 * n, dtype=dt, device=dev)
+    if grad:
+        out["grad_v"] = torch.empty(B, G, n, dtype=dt, device=dev)
+        out["grad_x"] = torch.empty(B, G, n, dtype=dt, device=dev)
+    rc = lib().hj_eval(HJ_H_QUADRATIC, C.byref(prob.H), HJ_J_ELLIPSOID, C.byref(prob.J),
+                       _ptr(x), B, n, float(wl.t), int(wl.nsteps), _ptr(v), G, C.byref(o),
+                       _ptr(out["phi"]), _ptr(out.get("yN")), _ptr(out["rho"]),
+                       _ptr(out.get("grad_v")), _ptr(out.get("grad_x")))
+    _check(rc)
+    return out
+
+
+class HJFunctional(torch.autograd.Function):
+    """The discretised Lax / Hopf objective as a differentiable function of
+    (x, v): forward is the RK4 solve with quadrature, backward the discrete
+    adjoint, both in libhj.so.  x [B, n], v [B, G, n] -> phi [B, G] (float64)."""
+
+    @staticmethod
+    def forward(ctx, x, v, wl):
+        out = evaluate(wl, x.contiguous(), v.contiguous(), grad=False)
+        ctx.save_for_backward(x, v)
+        ctx.wl = wl
+        return out["phi"]
+
+    @staticmethod
+    def backward(ctx, gphi):
+        x, v = ctx.saved_tensors
+        out = evaluate(ctx.wl, x.contiguous(), v.contiguous(), grad=True)
+        g = gphi.to(out["grad_v"].dtype)
+        gv = out["grad_v"] * g.unsqueeze(-1)
+        gx = (out["grad_x"] * g.unsqueeze(-1)).sum(dim=1)
+        return gx, gv, None
+
+
+def version() -> int:
+    return lib().hj_version()

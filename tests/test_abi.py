@@ -1,0 +1,110 @@
+"""Host-only checks of the C interface: the library loads, exports every
+function declared in include/hj.h, and rejects bad arguments before any
+device work (so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hj.h")
+LIB = os.path.join(ROOT, "paper_1704_02524_amd", "libhj.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int32_t|size_t|const char \*)\s*(hj_\w+)\s*\(", txt,
+                                 re.M)))
+
+
+def _need_lib():
+    if not os.path.exists(LIB):
+        from paper_1704_02524_amd import build
+        build.build()
+
+
+def test_header_declares_the_entry_points():
+    assert set(_declared()) >= {"hj_solve", "hj_eval", "hj_workspace_size", "hj_last_error",
+                                "hj_version"}
+
+
+def test_library_exports_every_declared_symbol():
+    _need_lib()
+    L = C.CDLL(LIB)
+    for name in _declared():
+        assert hasattr(L, name), name
+    L.hj_version.restype = C.c_int32
+    assert L.hj_version() == 1
+
+
+def _wl():
+    from paper_1704_02524_amd import workloads as W
+    return W.c1_hopf_n10(B=2)
+
+
+def _call_solve(wl, B=2, n=None, t=None, nsteps=None, G=4, R=2, xptr=1, **opt):
+    from paper_1704_02524_amd import hj
+    L = hj.lib()
+    prob = hj.Problem(wl)
+    o = hj.Opts()
+    for k, v in dict(dtype=0, formula=1, mode=1, quad=1, max_iter=10, ckpt_K=16, cert_fp64=1,
+                     alpha0=0.3, fd_sigma=1e-4, eps_step=1e-10, cert_tol=1e-8, v_max=1e6,
+                     acc_rel=1e-14).items():
+        setattr(o, k, v)
+    for k, v in opt.items():
+        setattr(o, k, v)
+    gs = hj.Guesses(G, R, C.c_void_p(1))
+    rc = L.hj_solve(0, C.byref(prob.H), 0, C.byref(prob.J), C.c_void_p(xptr), B,
+                    wl.n if n is None else n, wl.t if t is None else t,
+                    wl.nsteps if nsteps is None else nsteps, C.byref(gs), C.byref(o),
+                    C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None)
+    return rc, L.hj_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), -1), (dict(n=200), -5), (dict(t=0.0), -1), (dict(t=-1.0), -1),
+    (dict(t=float("nan")), -1), (dict(nsteps=0), -1), (dict(G=0), -1), (dict(G=65), -1),
+    (dict(R=-1), -1), (dict(B=-3), -1), (dict(dtype=7), -2), (dict(mode=5), -1),
+    (dict(quad=9), -1), (dict(max_iter=-1), -1), (dict(ckpt_K=0), -1), (dict(alpha0=0.0), -1),
+])
+def test_invalid_arguments_are_rejected(kw, code):
+    rc, msg = _call_solve(_wl(), **kw)
+    assert rc == code
+    assert msg
+
+
+def test_zero_points_is_a_noop():
+    rc, msg = _call_solve(_wl(), B=0, xptr=0)
+    assert rc == 0 and msg == ""
+
+
+def test_unknown_kinds_and_drift_are_reported():
+    from paper_1704_02524_amd import hj
+    wl = _wl()
+    L = hj.lib()
+    prob = hj.Problem(wl)
+    gs = hj.Guesses(4, 2, C.c_void_p(1))
+    rc = L.hj_solve(3, C.byref(prob.H), 0, C.byref(prob.J), C.c_void_p(1), 2, wl.n, wl.t,
+                    wl.nsteps, C.byref(gs), None, C.c_void_p(1), C.c_void_p(1),
+                    C.c_void_p(1), None)
+    assert rc == -5
+    bad_a = np.array(wl.a)
+    bad_a[3] = 0.0
+    prob2 = hj.Problem(wl.with_(a=bad_a))
+    rc = L.hj_solve(0, C.byref(prob2.H), 0, C.byref(prob2.J), C.c_void_p(1), 2, wl.n, wl.t,
+                    wl.nsteps, C.byref(gs), None, C.c_void_p(1), C.c_void_p(1),
+                    C.c_void_p(1), None)
+    assert rc == -1
+
+
+def test_workspace_size_grows_with_the_problem():
+    from paper_1704_02524_amd import hj
+    L = hj.lib()
+    o = hj.make_opts.__wrapped__ if hasattr(hj.make_opts, "__wrapped__") else None
+    assert o is None
+    small = L.hj_workspace_size(10, 16, 4, 128, None)
+    big = L.hj_workspace_size(10, 4096, 16, 128, None)
+    assert 0 < small < big
+    assert L.hj_workspace_size(0, 16, 4, 128, None) == 0

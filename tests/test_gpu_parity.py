@@ -1,0 +1,249 @@
+"""Parity of the HIP path (through the C interface) with the FP64 CPU
+reference on the same seeded inputs.
+
+Tolerances: objective values at fixed v agree to 1e-12 relative in FP64 and
+1e-4 in FP32; exact gradients to 1e-10; full solves to 1e-9 max(1, |u|) in
+FP64 and 1e-4 max(1, |u|) in FP32, with equal certificate flags and argopt to
+1e-6 (FP64) where certified.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle, build as build_oracle
+from paper_1704_02524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+build_oracle()
+
+
+@pytest.fixture(scope="module")
+def hj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_02524_amd import hj as _hj
+    return _hj
+
+
+def _dev(a, wl):
+    dt = torch.float64 if wl.dtype == W.F64 else torch.float32
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda().contiguous()
+
+
+def _family(n, formula, m_kind, e, quad, nsteps=24, signs=False, w=0.0, B=5, G=3, seed=0,
+            dtype=W.F64):
+    rng = np.random.default_rng(seed)
+    d = np.ones(n)
+    if signs:
+        d[0] = -1.0
+    a = rng.uniform(1.3, 2.0, n)
+    wl = W.Workload(name="family", n=n, t=0.6, nsteps=nsteps, m_kind=m_kind, e=e, kappa=0.4,
+                    s=float(n), w=w, d=d, A=None, a=a, j0=-0.5, formula=formula, quad=quad,
+                    x=rng.uniform(-1.5, 1.5, (B, n)), guesses=rng.standard_normal((B, G, 3, n)),
+                    dtype=dtype)
+    return W._as_dtype(wl) if dtype == W.F32 else wl
+
+
+EVAL_CASES = [
+    # n, formula, m_kind, e, quad, signs, w
+    (1, W.LAX, W.M_RAT, 2, W.TRAPZ, False, 0.0),
+    (2, W.LAX, W.M_RAT, 2, W.TRAPZ, False, 0.0),
+    (3, W.HOPF, W.M_TANH, 1, W.RK4AUG, True, 0.0),
+    (10, W.HOPF, W.M_TANH, 1, W.RK4AUG, True, 0.0),
+    (7, W.LAX, W.M_CONST, 1, W.RK4AUG, False, 0.7),
+    (13, W.HOPF, W.M_RAT, 1, W.TRAPZ, True, -0.3),
+    (32, W.LAX, W.M_TANH, 2, W.RK4AUG, False, 0.0),
+    (100, W.LAX, W.M_TANH, 1, W.RK4AUG, False, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", EVAL_CASES, ids=lambda c: f"n{c[0]}_f{c[1]}_m{c[2]}")
+def test_eval_matches_reference_fp64(hj, case):
+    n, formula, m_kind, e, quad, signs, w = case
+    wl = _family(n, formula, m_kind, e, quad, signs=signs, w=w)
+    v = wl.guesses[:, :, 0, :].copy()
+    out = hj.evaluate(wl, _dev(wl.x, wl), _dev(v, wl), grad=True, yN=True, ckpt_K=5)
+    torch.cuda.synchronize()
+    o = Oracle.from_workload(wl)
+    for b in range(wl.B):
+        for g in range(wl.G):
+            phi, yN = o.eval(wl.x[b], v[b, g])
+            _, gv, gx = o.grad_tangent(wl.x[b], v[b, g])
+            tol = 1e-12 * max(1.0, abs(phi))
+            assert abs(out["phi"][b, g].item() - phi) <= tol
+            np.testing.assert_allclose(out["yN"][b, g].cpu().numpy(), yN, rtol=1e-12,
+                                       atol=1e-12 * np.abs(yN).max())
+            assert out["rho"][b, g].item() == pytest.approx(o.certificate(yN), rel=1e-9,
+                                                            abs=1e-12)
+            gsc = max(1.0, np.abs(gv).max())
+            np.testing.assert_allclose(out["grad_v"][b, g].cpu().numpy(), gv, rtol=0,
+                                       atol=1e-10 * gsc)
+            gsc = max(1.0, np.abs(gx).max())
+            np.testing.assert_allclose(out["grad_x"][b, g].cpu().numpy(), gx, rtol=0,
+                                       atol=1e-10 * gsc)
+
+
+@pytest.mark.parametrize("n", [2, 10, 100])
+def test_eval_matches_reference_fp32(hj, n):
+    wl = _family(n, W.LAX if n != 10 else W.HOPF, W.M_TANH, 1, W.RK4AUG, signs=(n == 10),
+                 dtype=W.F32)
+    v = wl.guesses[:, :, 0, :].copy()
+    out = hj.evaluate(wl, _dev(wl.x, wl), _dev(v, wl), grad=True, ckpt_K=8)
+    torch.cuda.synchronize()
+    o = Oracle.from_workload(wl)
+    for b in range(wl.B):
+        for g in range(wl.G):
+            phi, _ = o.eval(wl.x[b], v[b, g])
+            _, gv, _ = o.grad_tangent(wl.x[b], v[b, g])
+            assert abs(out["phi"][b, g].item() - phi) <= 1e-4 * max(1.0, abs(phi))
+            np.testing.assert_allclose(out["grad_v"][b, g].cpu().numpy(), gv, rtol=0,
+                                       atol=1e-3 * max(1.0, np.abs(gv).max()))
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(hj):
+    wl = _family(10, W.HOPF, W.M_TANH, 1, W.RK4AUG, signs=True, nsteps=37)
+    x, v = _dev(wl.x, wl), _dev(wl.guesses[:, :, 0, :].copy(), wl)
+    ref = hj.evaluate(wl, x, v, grad=True, ckpt_K=1)
+    for K in [2, 5, 16, 37, 64]:
+        out = hj.evaluate(wl, x, v, grad=True, ckpt_K=K)
+        assert torch.equal(out["grad_v"], ref["grad_v"]), K
+        assert torch.equal(out["phi"], ref["phi"]), K
+
+
+def _compare_solve(res, ref, wl, tol_u, tol_arg):
+    u = res["u"].cpu().numpy()
+    cert = res["cert"].cpu().numpy()
+    arg = res["argopt"].cpu().numpy()
+    np.testing.assert_array_equal(cert, ref["cert"])
+    fin = ref["cert"] >= 0
+    err = np.abs(u[fin] - ref["u"][fin]) / np.maximum(1.0, np.abs(ref["u"][fin]))
+    assert err.max(initial=0.0) <= tol_u, err.max()
+    c1 = ref["cert"] == 1
+    if c1.any():
+        aerr = np.abs(arg[c1] - ref["argopt"][c1]).max() / max(1.0, np.abs(ref["argopt"][c1]).max())
+        assert aerr <= tol_arg, aerr
+
+
+def _oracle_solve(wl):
+    return Oracle.from_workload(wl).solve(wl.x, wl.guesses, Oracle.opts_from_workload(wl))
+
+
+def test_solve_lax_n2_cd_matches_reference(hj):
+    wl = W.c0_lax_n2(B=1024)
+    idx = np.r_[0:24, 500:516, 1000:1024]
+    sub = wl.with_(x=wl.x[idx].copy(), guesses=wl.guesses[idx].copy())
+    res = hj.solve(sub, *hj.device_inputs(sub))
+    ref = _oracle_solve(sub)
+    torch.cuda.synchronize()
+    _compare_solve(res, ref, sub, 1e-9, 1e-6)
+    # the descent path is the same: iteration and solve counts agree
+    np.testing.assert_array_equal(res["slot_fwd"].cpu().numpy(), ref["slot_fwd"])
+
+
+@pytest.mark.parametrize("mode", [W.GD_ADJ, W.CD_FD])
+def test_solve_hopf_n10_matches_reference(hj, mode):
+    wl = W.c1_hopf_n10(B=4096, mode=mode)
+    idx = [0, 1, 2, 3, 1234, 4095] if mode == W.GD_ADJ else [0, 4095]
+    G = 16 if mode == W.GD_ADJ else 4
+    sub = wl.with_(x=wl.x[idx].copy(), guesses=wl.guesses[idx, :G].copy())
+    res = hj.solve(sub, *hj.device_inputs(sub))
+    ref = _oracle_solve(sub)
+    torch.cuda.synchronize()
+    _compare_solve(res, ref, sub, 1e-9, 1e-6)
+    assert (ref["cert"] == 1).all()
+
+
+def test_solve_full_size_hopf_n10_sampled(hj):
+    """The full 4096-point, 16-guess launch; a sample of points is checked
+    against the reference one by one."""
+    wl = W.c1_hopf_n10(B=4096)
+    res = hj.solve(wl, *hj.device_inputs(wl))
+    torch.cuda.synchronize()
+    cert = res["cert"].cpu().numpy()
+    assert (cert == 1).mean() > 0.99
+    sample = [7, 2048, 4000] + list(np.where(cert != 1)[0][:2])
+    for b in sample:
+        sub = wl.subset(b, b + 1)
+        ref = _oracle_solve(sub)
+        part = {k: v[b:b + 1] for k, v in res.items() if k in ("u", "cert", "argopt")}
+        _compare_solve(part, ref, sub, 1e-9, 1e-6)
+
+
+@pytest.mark.parametrize("n,mode", [(3, W.GD_ADJ), (5, W.CD_FD), (13, W.GD_ADJ),
+                                    (17, W.GD_ADJ)])
+def test_solve_ragged_dimensions(hj, n, mode):
+    wl = _family(n, W.HOPF, W.M_TANH, 1, W.RK4AUG, signs=True, B=3, G=2).with_(
+        mode=mode, max_iter=120 if mode == W.GD_ADJ else 80, eps_step=1e-12, cert_tol=1e-6,
+        alpha0=1 / 3)
+    res = hj.solve(wl, *hj.device_inputs(wl))
+    ref = _oracle_solve(wl)
+    torch.cuda.synchronize()
+    _compare_solve(res, ref, wl, 1e-9, 1e-6)
+
+
+def test_solve_fp32_with_fp64_certificate(hj):
+    wl = W.c4_lax_n100(B=4).with_(guesses=W.c4_lax_n100(B=4).guesses[:, :2].copy(),
+                                 max_iter=120)
+    res = hj.solve(wl, *hj.device_inputs(wl))
+    ref = _oracle_solve(wl)
+    torch.cuda.synchronize()
+    u = res["u"].cpu().numpy()
+    np.testing.assert_array_equal(res["cert"].cpu().numpy(), ref["cert"])
+    assert (np.abs(u - ref["u"]) / np.maximum(1, np.abs(ref["u"]))).max() <= 1e-4
+    arg = res["argopt"].cpu().numpy()
+    assert np.abs(arg - ref["argopt"]).max() <= 5e-3 * max(1.0, np.abs(ref["argopt"]).max())
+
+
+def test_failure_paths(hj):
+    """NaN guesses diverge, tolerance 0 certifies nothing, an ill-posed Hopf
+    instance never certifies; all as in the reference."""
+    wl = W.c1_hopf_n10(B=3)
+    wl = wl.with_(guesses=wl.guesses[:, :2].copy())
+    g = wl.guesses.copy()
+    g[0, 0] = np.nan
+    g[1] = np.nan
+    w1 = wl.with_(guesses=g)
+    res = hj.solve(w1, *hj.device_inputs(w1))
+    ref = _oracle_solve(w1)
+    _compare_solve(res, ref, w1, 1e-9, 1e-6)
+    assert res["cert"][1].item() == -1 and np.isnan(res["u"][1].item())
+    w2 = wl.with_(cert_tol=0.0)
+    res = hj.solve(w2, *hj.device_inputs(w2))
+    ref = _oracle_solve(w2)
+    _compare_solve(res, ref, w2, 1e-9, 1e-6)
+    assert (res["cert"].cpu().numpy() == 0).all()
+    a = wl.a.copy()
+    a[0] = 0.8
+    w3 = wl.with_(a=a, v_max=1e3)
+    res = hj.solve(w3, *hj.device_inputs(w3))
+    torch.cuda.synchronize()
+    assert (res["cert"].cpu().numpy() <= 0).all()
+
+
+def test_solve_is_deterministic(hj):
+    wl = W.c1_hopf_n10(B=64)
+    x, g = hj.device_inputs(wl)
+    a = hj.solve(wl, x, g)
+    b = hj.solve(wl, x, g)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k].nan_to_num(), b[k].nan_to_num()), k
+
+
+def test_autograd_functional(hj):
+    wl = _family(6, W.HOPF, W.M_TANH, 1, W.RK4AUG, signs=True, B=3, G=2)
+    x = _dev(wl.x, wl).requires_grad_(True)
+    v = _dev(wl.guesses[:, :, 0, :].copy(), wl).requires_grad_(True)
+    phi = hj.HJFunctional.apply(x, v, wl)
+    (phi * torch.arange(1, 7, device=phi.device, dtype=phi.dtype).view(3, 2)).sum().backward()
+    o = Oracle.from_workload(wl)
+    for b in range(3):
+        gx_ref = np.zeros(6)
+        for g in range(2):
+            _, gv, gx = o.grad_tangent(wl.x[b], wl.guesses[b, g, 0])
+            w = 2 * b + g + 1
+            np.testing.assert_allclose(v.grad[b, g].cpu().numpy(), w * gv, rtol=1e-10,
+                                       atol=1e-10)
+            gx_ref += w * gx
+        np.testing.assert_allclose(x.grad[b].cpu().numpy(), gx_ref, rtol=1e-10, atol=1e-10)
