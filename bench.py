@@ -52,13 +52,13 @@ def algorithmic_flops(wl, slot_fwd, slot_bwd):
         float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps)
 
 
-def run_gpu(wl, steps, warmup, label):
+def run_gpu(wl, steps, warmup, label, cfg=None):
     import torch
     from paper_1704_02524_amd import hj
     x, g = hj.device_inputs(wl)
     out = None
     for i in range(warmup):
-        out = hj.solve(wl, x, g, out=out)
+        out = hj.solve(wl, x, g, out=out, **(cfg or {}))
         torch.cuda.synchronize()
         log(f"{label}: warmup {i + 1}/{warmup} done")
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -71,7 +71,7 @@ def run_gpu(wl, steps, warmup, label):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        out = hj.solve(wl, x, g, out=out, events=evs[i])
+        out = hj.solve(wl, x, g, out=out, events=evs[i], **(cfg or {}))
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     kern_ms = [a.elapsed_time(b) for a, b in evs]
@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--points", type=int, default=4096)
     ap.add_argument("--no-cd", action="store_true", help="skip the central-FD comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
@@ -117,12 +118,15 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1704_02524_amd import tune
     from paper_1704_02524_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     wl = W.c1_hopf_n10(B=args.points, mode=W.GD_ADJ)
     log(f"workload {wl.name}: B={wl.B} G={wl.G} n={wl.n} N={wl.nsteps}")
-    wall, kern, host = run_gpu(wl, args.steps, args.warmup, "adjoint GD")
+    cfg = {} if args.no_tune else tune.tune(wl, verbose=True)
+    log(f"launch configuration: {cfg or 'library default'}")
+    wall, kern, host = run_gpu(wl, args.steps, args.warmup, "adjoint GD", cfg)
     n_cert = int((host["cert"] == 1).sum())
     value = n_cert / wall
     flops = algorithmic_flops(wl, host["slot_fwd"], host["slot_bwd"])
@@ -153,14 +157,15 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-            "kernel": "k_solve_gd<double,10,1>", "kernel_ms": float(np.mean(kern)),
+            "kernel": "k_solve_gd", "launch": cfg, "kernel_ms": float(np.mean(kern)),
             "algorithmic_flops_per_launch": flops,
         },
     }
     if not args.no_cd:
         wcd = wl.with_(mode=W.CD_FD)
-        run_gpu(wcd.subset(0, 64), 1, 0, "CD warm")
-        wall_cd, kern_cd, host_cd = run_gpu(wcd, 1, 0, "central-FD CD")
+        cfg_cd = {} if args.no_tune else tune.tune(wcd, tune_iters=2, verbose=True)
+        log(f"launch configuration (CD): {cfg_cd or 'library default'}")
+        wall_cd, kern_cd, host_cd = run_gpu(wcd, 1, 0, "central-FD CD", cfg_cd)
         fin = (host["cert"] >= 0) & (host_cd["cert"] >= 0)
         du = np.abs(host["u"][fin] - host_cd["u"][fin]) / np.maximum(1, np.abs(host["u"][fin]))
         flops_cd = algorithmic_flops(wcd, host_cd["slot_fwd"], host_cd["slot_bwd"])

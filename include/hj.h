@@ -109,7 +109,11 @@ typedef struct {
     int32_t ckpt_K;       /* adjoint checkpoint interval in steps (>= 1)   */
     int32_t cert_fp64;    /* HJ_F32: re-evaluate objective and certificate
                              in FP64 at each run's final v                 */
-    int32_t reserved;
+    int32_t lanes_per_task; /* 0: the library's choice; else 1, 2, 4, 8 or
+                             16 lanes of a wavefront share one (point,
+                             guess) task, each holding ceil(n / lanes)
+                             components (HJ_EUNSUPPORTED if no such
+                             kernel is built)                              */
     double  alpha0;       /* initial step size (1/L of Algorithm 1)        */
     double  fd_sigma;     /* central-difference step                       */
     double  eps_step;     /* stop when an iteration's largest move < this  */

@@ -1,6 +1,6 @@
 // hj_api.hip -- host side of the C interface declared in include/hj.h:
 // argument checks, parameter staging, workspace layout, and the dispatch of
-// the templated kernels by (dtype, components per lane, lanes per task).
+// the kernel instances by (dtype, lane shape, speed profile).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,9 +12,11 @@
 #include <vector>
 
 #include "hj.h"
-#include "hj_kernels.hpp"
+#include "hj_launch.hpp"
 
 namespace {
+
+using hj::Shape;
 
 thread_local std::string g_last_error;
 
@@ -40,21 +42,24 @@ DevScratch g_ws[64];
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Vector layout: components per lane (NPL) and lanes per task (LPT) by n.
-struct Shape {
-  int npl, lpt;
-  int npad() const { return npl * lpt; }
-};
-
-bool pick_shape(int n, Shape& s) {
-  static const Shape table[] = {{2, 1}, {4, 1}, {8, 1}, {10, 1}, {8, 2},
-                                {8, 4}, {8, 8}, {13, 8}, {16, 8}};
-  for (const Shape& t : table)
-    if (n <= t.npad()) {
+// The lane shape for n: with lpt == 0 the first default shape covering n,
+// else the smallest compiled shape with that many lanes per task.
+bool pick_shape(int n, int lpt, Shape& s) {
+  if (lpt == 0) {
+    for (int i = 0; i < hj::kNumDefaultShapes; ++i)
+      if (n <= hj::kShapes[i].npad()) {
+        s = hj::kShapes[i];
+        return true;
+      }
+    return false;
+  }
+  bool found = false;
+  for (const Shape& t : hj::kShapes)
+    if (t.lpt == lpt && n <= t.npad() && (!found || t.npl < s.npl)) {
       s = t;
-      return true;
+      found = true;
     }
-  return false;
+  return found;
 }
 
 // Layout of the scratch memory of one call.
@@ -63,11 +68,9 @@ struct WsLayout {
   size_t stride = 0;  // lanes of the SoA checkpoint arrays
 };
 
-WsLayout layout(int n, int64_t B, int G, int nsteps, int dtype, int mode, int K, bool grad,
-                bool solve) {
+WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
+                bool grad, bool solve) {
   WsLayout L;
-  Shape s{};
-  pick_shape(n, s);
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
   const size_t BG = (size_t)B * (size_t)G;
   size_t off = 0;
@@ -164,25 +167,32 @@ HostParams<T> host_params(const hj_h_params* H, const hj_j_params* J, int n, int
   return p;
 }
 
+// Kernel speed profile: TANH, or RAT (which with kappa = 0 is CONST).
+int kernel_mk(const hj_h_params* H) { return H->m_kind == HJ_M_TANH ? HJ_M_TANH : HJ_M_RAT; }
+
 template <typename T>
 hj::Problem<T> make_problem(const hj_h_params* H, const hj_j_params* J, int n, double t,
-                            int nsteps, int formula, int quad, const T* dev) {
+                            int nsteps, int formula, int quad, const T* base, int npad) {
   hj::Problem<T> P;
   P.n = n;
   P.N = nsteps;
-  P.m_kind = H->m_kind;
   P.e = H->e;
   P.formula = formula;
   P.quad = quad;
-  P.kappa = (T)H->kappa;
+  P.kappa = (T)(H->m_kind == HJ_M_CONST ? 0.0 : H->kappa);
   P.inv_s = (T)(H->m_kind == HJ_M_TANH ? 1.0 / H->s : 1.0);
   P.w = (T)H->w;
   P.j0 = (T)J->j0;
   P.h = (T)(t / nsteps);
+  P.d = base;
+  P.a2 = base + npad;
+  P.ia2 = base + 2 * npad;
   return P;
 }
 
-// Stage d, a^2, 1/a^2 (in T and in double) into the params region.
+// Stage d, a^2, 1/a^2 (in T and in double) into the params region.  The copy
+// is ordered on the stream after any earlier call's kernels that read the
+// region, and completes before the host buffer goes out of scope.
 template <typename T>
 int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, char* region,
                  hipStream_t st, const T** dT, const double** dD) {
@@ -197,7 +207,6 @@ int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, ch
   std::memcpy(q2, pd.d.data(), npad * 8);
   std::memcpy(q2 + npad * 8, pd.a2.data(), npad * 8);
   std::memcpy(q2 + 2 * npad * 8, pd.ia2.data(), npad * 8);
-  // pageable source: the copy is staged before the call returns
   HJ_HIP(hipMemcpyAsync(region, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
   HJ_HIP(hipStreamSynchronize(st));
   *dT = reinterpret_cast<const T*>(region);
@@ -205,78 +214,44 @@ int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, ch
   return HJ_OK;
 }
 
+// Launchers by shape and speed profile.
 template <typename T>
-void bind(hj::Problem<T>& P, const T* base, int npad) {
-  P.d = base;
-  P.a2 = base + npad;
-  P.ia2 = base + 2 * npad;
+hipError_t dispatch_solve(const Shape& s, int mk, const hj::SolveArgs<T>& A, int mode,
+                          hipStream_t st) {
+#define HJ_CASE(NPL, LPT)                                                               \
+  if (s.npl == NPL && s.lpt == LPT)                                                     \
+    return mk == HJ_M_TANH                                                              \
+               ? hj::launch_solve<hj::Cfg<T, NPL, LPT, HJ_M_TANH>>(A, mode, st)         \
+               : hj::launch_solve<hj::Cfg<T, NPL, LPT, HJ_M_RAT>>(A, mode, st);
+  HJ_FOR_EACH_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return hipErrorInvalidValue;
 }
 
-template <typename T, int NPL, int LPT>
-int launch_solve(const hj::SolveArgs<T>& A, int mode, hipStream_t st) {
-  const int64_t threads = A.B * A.G * LPT;
-  const int block = 256;
-  const int64_t grid = (threads + block - 1) / block;
-  if (mode == HJ_CD_FD)
-    hipLaunchKernelGGL((hj::k_solve_cd<T, NPL, LPT>), dim3((unsigned)grid), dim3(block), 0, st, A);
-  else
-    hipLaunchKernelGGL((hj::k_solve_gd<T, NPL, LPT>), dim3((unsigned)grid), dim3(block), 0, st, A);
-  HJ_HIP(hipGetLastError());
-  return HJ_OK;
+template <typename T>
+hipError_t dispatch_eval(const Shape& s, int mk, const hj::EvalArgs<T>& A, hipStream_t st) {
+#define HJ_CASE(NPL, LPT)                                                               \
+  if (s.npl == NPL && s.lpt == LPT)                                                     \
+    return mk == HJ_M_TANH ? hj::launch_eval<hj::Cfg<T, NPL, LPT, HJ_M_TANH>>(A, st)    \
+                           : hj::launch_eval<hj::Cfg<T, NPL, LPT, HJ_M_RAT>>(A, st);
+  HJ_FOR_EACH_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return hipErrorInvalidValue;
 }
-
-template <typename T, int NPL, int LPT>
-int launch_eval(const hj::EvalArgs<T>& A, const hj_opts* o, hipStream_t st) {
-  const int64_t threads = A.B * A.G * LPT;
-  const int block = 256;
-  const int64_t grid = (threads + block - 1) / block;
-  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
-  hipLaunchKernelGGL((hj::k_eval<T, NPL, LPT>), dim3((unsigned)grid), dim3(block), 0, st, A);
-  HJ_HIP(hipGetLastError());
-  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
-  return HJ_OK;
-}
-
-// The descent kernel followed by the selection kernel.
-template <typename T, int NPL, int LPT>
-int launch_solve_then_select(const hj::SolveArgs<T>& A, const hj_opts* o, hipStream_t st,
-                             double* out_u, void* out_argopt, int32_t* out_cert) {
-  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
-  int rc = launch_solve<T, NPL, LPT>(A, o->mode, st);
-  if (rc) return rc;
-  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
-  const int block = 256;
-  const int64_t grid = (A.B + block - 1) / block;
-  hipLaunchKernelGGL((hj::k_select<T>), dim3((unsigned)grid), dim3(block), 0, st, A.B, A.G, A.P.n,
-                     A.P.formula, A.out.phi, A.out.cert, A.out.v, out_u,
-                     static_cast<T*>(out_argopt), out_cert);
-  HJ_HIP(hipGetLastError());
-  return HJ_OK;
-}
-
-#define HJ_DISPATCH(SHAPE, FN, ...)                                  \
-  switch (SHAPE.npl * 100 + SHAPE.lpt) {                             \
-    case 201: return FN<T, 2, 1>(__VA_ARGS__);                       \
-    case 401: return FN<T, 4, 1>(__VA_ARGS__);                       \
-    case 801: return FN<T, 8, 1>(__VA_ARGS__);                       \
-    case 1001: return FN<T, 10, 1>(__VA_ARGS__);                     \
-    case 802: return FN<T, 8, 2>(__VA_ARGS__);                       \
-    case 804: return FN<T, 8, 4>(__VA_ARGS__);                       \
-    case 808: return FN<T, 8, 8>(__VA_ARGS__);                       \
-    case 1308: return FN<T, 13, 8>(__VA_ARGS__);                     \
-    case 1608: return FN<T, 16, 8>(__VA_ARGS__);                     \
-    default: return fail(HJ_EUNSUPPORTED, "no kernel for this n");  \
-  }
 
 template <typename T>
 int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B, int n,
             double t, int nsteps, const hj_guesses* gs, const hj_opts* o, double* out_u,
             void* out_argopt, int32_t* out_cert, const hj_slot_diag* diag) {
   Shape s{};
-  pick_shape(n, s);
+  if (!pick_shape(n, o->lanes_per_task, s))
+    return fail(HJ_EUNSUPPORTED, "no kernel with " + std::to_string(o->lanes_per_task) +
+                                     " lanes per task for n = " + std::to_string(n));
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
-  WsLayout WL = layout(n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true);
+  WsLayout WL = layout(s, n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true);
+  if ((size_t)B * gs->G * s.lpt > (size_t)UINT32_MAX * 128)
+    return fail(HJ_EINVAL, "B * G too large for one launch");
   void* ws = nullptr;
   int rc = get_workspace(o, WL.total, &ws);
   if (rc) return rc;
@@ -288,10 +263,8 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   if (rc) return rc;
 
   hj::SolveArgs<T> A;
-  A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT);
-  bind(A.P, dT, npad);
-  A.P64 = make_problem<double>(H, J, n, t, nsteps, o->formula, o->quad, dD);
-  bind(A.P64, dD, npad);
+  A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT, npad);
+  A.P64 = make_problem<double>(H, J, n, t, nsteps, o->formula, o->quad, dD, npad);
   A.x = static_cast<const T*>(x);
   A.guesses = static_cast<const T*>(gs->init);
   A.B = B;
@@ -310,7 +283,7 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   A.stride = WL.stride;
   A.ck = WL.ck ? reinterpret_cast<T*>(base + WL.ck) : nullptr;
   A.seg = WL.seg ? reinterpret_cast<T*>(base + WL.seg) : nullptr;
-  // per-slot records: caller's diag arrays where given, else scratch
+  // per-slot records: the caller's diag arrays where given, else scratch
   const size_t BG = (size_t)B * gs->G;
   char* sp = base + WL.slots;
   double* w_phi = reinterpret_cast<double*>(sp);
@@ -332,7 +305,12 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   A.out.n_bwd = (diag && diag->n_bwd) ? diag->n_bwd : w_bwd;
   A.out.v = (diag && diag->v_final) ? static_cast<T*>(diag->v_final) : w_v;
 
-  HJ_DISPATCH(s, launch_solve_then_select, A, o, st, out_u, out_argopt, out_cert);
+  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
+  HJ_HIP(dispatch_solve<T>(s, kernel_mk(H), A, o->mode, st));
+  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
+  HJ_HIP(hj::launch_select<T>(B, gs->G, n, o->formula, A.out.phi, A.out.cert, A.out.v, out_u,
+                              static_cast<T*>(out_argopt), out_cert, st));
+  return HJ_OK;
 }
 
 template <typename T>
@@ -340,11 +318,13 @@ int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B,
            double t, int nsteps, const void* v, int G, const hj_opts* o, double* out_phi,
            void* out_yN, double* out_rho, void* out_gv, void* out_gx) {
   Shape s{};
-  pick_shape(n, s);
+  if (!pick_shape(n, o->lanes_per_task, s))
+    return fail(HJ_EUNSUPPORTED, "no kernel with " + std::to_string(o->lanes_per_task) +
+                                     " lanes per task for n = " + std::to_string(n));
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
   const bool grad = out_gv || out_gx;
-  WsLayout WL = layout(n, B, G, nsteps, o->dtype, o->mode, K, grad, false);
+  WsLayout WL = layout(s, n, B, G, nsteps, o->dtype, o->mode, K, grad, false);
   void* ws = nullptr;
   int rc = get_workspace(o, WL.total, &ws);
   if (rc) return rc;
@@ -355,8 +335,7 @@ int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B,
   rc = stage_params<T>(H, J, n, npad, base + WL.params, st, &dT, &dD);
   if (rc) return rc;
   hj::EvalArgs<T> A;
-  A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT);
-  bind(A.P, dT, npad);
+  A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT, npad);
   A.x = static_cast<const T*>(x);
   A.v = static_cast<const T*>(v);
   A.B = B;
@@ -370,7 +349,10 @@ int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B,
   A.stride = WL.stride;
   A.ck = grad ? reinterpret_cast<T*>(base + WL.ck) : nullptr;
   A.seg = grad ? reinterpret_cast<T*>(base + WL.seg) : nullptr;
-  HJ_DISPATCH(s, launch_eval, A, o, st);
+  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
+  HJ_HIP(dispatch_eval<T>(s, kernel_mk(H), A, st));
+  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
+  return HJ_OK;
 }
 
 hj_opts default_opts() {
@@ -404,6 +386,7 @@ int check_opts(const hj_opts* o) {
   if (!(o->armijo_c >= 0.0 && o->armijo_c < 1.0))
     return fail(HJ_EINVAL, "armijo_c must be in [0, 1)");
   if (o->mode == HJ_CD_FD && !(o->fd_sigma > 0.0)) return fail(HJ_EINVAL, "fd_sigma must be > 0");
+  if (o->lanes_per_task < 0) return fail(HJ_EINVAL, "lanes_per_task must be >= 0");
   return HJ_OK;
 }
 
@@ -428,8 +411,6 @@ int32_t hj_solve(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_
   if (B == 0) return HJ_OK;
   if (!x || !guesses->init || !out_u || !out_argopt || !out_cert)
     return fail(HJ_EINVAL, "x, guesses->init and the outputs are required");
-  if (B * (int64_t)guesses->G * 16 > (int64_t)UINT32_MAX * 256 / 2)
-    return fail(HJ_EINVAL, "B * G too large for one launch");
   if (o.dtype == HJ_F64)
     return solve_t<double>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert,
                            diag);
@@ -460,10 +441,12 @@ int32_t hj_eval(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j
 size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const hj_opts* opts) {
   if (n < 1 || n > HJ_MAX_N || B < 0 || G < 1 || nsteps < 1) return 0;
   hj_opts o = opts ? *opts : default_opts();
+  Shape s{};
+  if (!pick_shape(n, o.lanes_per_task, s)) return 0;
   const int K = std::max(1, std::min(o.ckpt_K, nsteps));
   // the larger of what hj_solve and hj_eval (with gradients) need
-  WsLayout a = layout(n, B, G, nsteps, o.dtype, o.mode, K, false, true);
-  WsLayout b = layout(n, B, G, nsteps, o.dtype, o.mode, K, true, false);
+  WsLayout a = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, false, true);
+  WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
   return std::max(a.total, b.total);
 }
 

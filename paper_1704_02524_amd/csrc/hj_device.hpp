@@ -20,6 +20,14 @@ namespace hj {
 // ---------------------------------------------------------------------------
 // math helpers
 // ---------------------------------------------------------------------------
+// Coefficients 1/j! (j = 13 .. 2) of the Taylor polynomial of expm1, in
+// constant memory so that the wave-uniform loads land in scalar registers and
+// every Horner step is one v_fma_f64 with a scalar operand.
+static __constant__ double kExpm1Coef[12] = {
+    1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0,
+    1.0 / 362880.0,     1.0 / 40320.0,     1.0 / 5040.0,     1.0 / 720.0,
+    1.0 / 120.0,        1.0 / 24.0,        1.0 / 6.0,        0.5};
+
 // expm1(y) for y <= 0 in FP64: Cody-Waite reduction y = k ln2 + f with
 // |f| <= ln2/2 (ln2 split into a 32-bit head and a tail), Taylor polynomial
 // of expm1(f) to degree 13 (truncation below 1e-17 relative), and
@@ -31,33 +39,30 @@ __device__ __forceinline__ double expm1_neg(double y) {
   const double k = __builtin_rint(y * inv_ln2);
   double f = __builtin_fma(-k, ln2_hi, y);
   f = __builtin_fma(-k, ln2_lo, f);
-  // f + f^2/2! + ... + f^13/13!  (Horner on the coefficients 1/j!)
-  double p = 1.0 / 6227020800.0;                 // 1/13!
-  p = __builtin_fma(p, f, 1.0 / 479001600.0);    // 1/12!
-  p = __builtin_fma(p, f, 1.0 / 39916800.0);     // 1/11!
-  p = __builtin_fma(p, f, 1.0 / 3628800.0);      // 1/10!
-  p = __builtin_fma(p, f, 1.0 / 362880.0);       // 1/9!
-  p = __builtin_fma(p, f, 1.0 / 40320.0);        // 1/8!
-  p = __builtin_fma(p, f, 1.0 / 5040.0);         // 1/7!
-  p = __builtin_fma(p, f, 1.0 / 720.0);          // 1/6!
-  p = __builtin_fma(p, f, 1.0 / 120.0);          // 1/5!
-  p = __builtin_fma(p, f, 1.0 / 24.0);           // 1/4!
-  p = __builtin_fma(p, f, 1.0 / 6.0);            // 1/3!
-  p = __builtin_fma(p, f, 0.5);                  // 1/2!
+  double p = kExpm1Coef[0];
+#pragma unroll
+  for (int j = 1; j < 12; ++j) p = __builtin_fma(p, f, kExpm1Coef[j]);
   p = __builtin_fma(p * f, f, f);                // f + f^2 (1/2 + ...)
   const double s = __builtin_ldexp(1.0, (int)k); // exact; 0 for very negative k
   return __builtin_fma(s, p, s - 1.0);
 }
 
-// tanh in FP64 from expm1: tanh|z| = -e / (2 + e), e = expm1(-2|z|); exact
-// limit 1 for |z| > 20 (tanh(20) = 1 - 8e-18).
+// a / b for b in [1, 2]: hardware reciprocal, one Newton step and one
+// residual correction of the quotient (error about one ulp).
+__device__ __forceinline__ double div_1_2(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+
+// tanh in FP64 from expm1: tanh|z| = -e / (2 + e), e = expm1(-2|z|) in
+// (-1, 0].  |z| is clamped to 20 (tanh(20) rounds to 1), which keeps the
+// code branch-free.
 __device__ __forceinline__ double dtanh(double z) {
   const double az = __builtin_fabs(z);
-  double t = 1.0;
-  if (az <= 20.0) {
-    const double e = expm1_neg(-2.0 * az);
-    t = -e / (2.0 + e);
-  }
+  const double e = expm1_neg(-2.0 * (az < 20.0 ? az : 20.0));
+  double t = div_1_2(-e, 2.0 + e);
   if (z != z) t = z;
   return __builtin_copysign(t, z);
 }
@@ -71,26 +76,79 @@ template <typename T> __device__ __forceinline__ T nanmax(T s, T a) {
   return (a > s || a != a) ? a : s;
 }
 
-// Butterfly sum / max over the LPT lanes of a task group.  Addition is
-// commutative, so all lanes of the group end with the same bits.
+// Cross-lane exchange inside a row of 16 lanes with DPP (no LDS traffic).
+//   step 0: quad_perm [1,0,3,2]  (lane ^ 1)
+//   step 1: quad_perm [2,3,0,1]  (lane ^ 2)
+//   step 2: row_half_mirror      (lane i of 8 <-> 7 - i: swaps the two quads)
+//   step 3: row_mirror           (lane i of 16 <-> 15 - i: swaps the halves)
+// After step s every lane of an aligned group of 2^(s+1) lanes has combined
+// the same two partial values, so a butterfly of k steps reduces groups of
+// 2^k lanes and leaves bit-identical results in all of them (the combining
+// operations are commutative).
+template <int STEP> __device__ __forceinline__ int dpp_i(int v) {
+  constexpr int ctrl = STEP == 0 ? 0xB1 : STEP == 1 ? 0x4E : STEP == 2 ? 0x141 : 0x140;
+  return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
+}
+template <int STEP> __device__ __forceinline__ float dpp_x(float v) {
+  return __builtin_bit_cast(float, dpp_i<STEP>(__builtin_bit_cast(int, v)));
+}
+template <int STEP> __device__ __forceinline__ double dpp_x(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<STEP>((int)(unsigned)u);
+  const unsigned hi = (unsigned)dpp_i<STEP>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum / max over the LPT lanes of a task group (LPT in 1, 2, 4, 8, 16).
 template <int LPT, typename T> __device__ __forceinline__ T gsum(T v) {
-#pragma unroll
-  for (int o = LPT / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, LPT);
+  static_assert(LPT == 1 || LPT == 2 || LPT == 4 || LPT == 8 || LPT == 16, "LPT");
+  if (LPT >= 2) v += dpp_x<0>(v);
+  if (LPT >= 4) v += dpp_x<1>(v);
+  if (LPT >= 8) v += dpp_x<2>(v);
+  if (LPT >= 16) v += dpp_x<3>(v);
   return v;
 }
 template <int LPT, typename T> __device__ __forceinline__ T gmax(T v) {
-#pragma unroll
-  for (int o = LPT / 2; o >= 1; o >>= 1) v = nanmax(v, __shfl_xor(v, o, LPT));
+  if (LPT >= 2) v = nanmax(v, dpp_x<0>(v));
+  if (LPT >= 4) v = nanmax(v, dpp_x<1>(v));
+  if (LPT >= 8) v = nanmax(v, dpp_x<2>(v));
+  if (LPT >= 16) v = nanmax(v, dpp_x<3>(v));
   return v;
 }
 
+// Sum of NPL terms as a balanced tree (short dependency chains).
+template <int NPL, typename T> __device__ __forceinline__ T tree_sum(const T (&a)[NPL]) {
+  if constexpr (NPL == 1) {
+    return a[0];
+  } else {
+    constexpr int H = NPL / 2;
+    T lo[H], hi[NPL - H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) lo[k] = a[k];
+#pragma unroll
+    for (int k = H; k < NPL; ++k) hi[k - H] = a[k];
+    return tree_sum<H>(lo) + tree_sum<NPL - H>(hi);
+  }
+}
+
+
 // ---------------------------------------------------------------------------
+// compile-time configuration of a kernel instance
+// ---------------------------------------------------------------------------
+// T: arithmetic type; NPL: components per lane; LPT: lanes per task;
+// MK: speed profile (HJ_M_TANH, or HJ_M_RAT which also serves HJ_M_CONST
+// with kappa = 0: c = 1 and c' = c'' = 0 exactly).
+template <typename T_, int NPL_, int LPT_, int MK_> struct Cfg {
+  using T = T_;
+  static constexpr int NPL = NPL_;
+  static constexpr int LPT = LPT_;
+  static constexpr int MK = MK_;
+};
+
 // problem description, in the arithmetic type T
-// ---------------------------------------------------------------------------
 template <typename T> struct Problem {
   int n;        // true dimension
   int N;        // RK4 steps
-  int m_kind;   // HJ_M_*
   int e;        // 1 or 2
   int formula;  // HJ_LAX / HJ_HOPF
   int quad;     // HJ_TRAPZ / HJ_RK4AUG
@@ -102,36 +160,36 @@ template <typename T> struct Problem {
 
 // Per-lane copy of the component parameters (uniform across the wave when
 // LPT == 1, so the compiler keeps them in scalar registers).
-template <typename T, int NPL> struct LaneParams {
-  T d[NPL], a2[NPL], ia2[NPL];
+template <class C> struct LaneParams {
+  using T = typename C::T;
+  T d[C::NPL], a2[C::NPL], ia2[C::NPL];
   __device__ __forceinline__ void load(const Problem<T>& P, int sub) {
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      d[k] = P.d[sub * NPL + k];
-      a2[k] = P.a2[sub * NPL + k];
-      ia2[k] = P.ia2[sub * NPL + k];
+    for (int k = 0; k < C::NPL; ++k) {
+      d[k] = P.d[sub * C::NPL + k];
+      a2[k] = P.a2[sub * C::NPL + k];
+      ia2[k] = P.ia2[sub * C::NPL + k];
     }
   }
 };
 
 // m = c^e and its derivatives in r = |gamma|^2.
-template <typename T, bool NEED2>
-__device__ __forceinline__ void speed(const Problem<T>& P, T r, T& m, T& m1, T& m2) {
+template <class C, bool NEED2>
+__device__ __forceinline__ void speed(const Problem<typename C::T>& P, typename C::T r,
+                                      typename C::T& m, typename C::T& m1, typename C::T& m2) {
+  using T = typename C::T;
   T c, c1, c2 = T(0);
-  if (P.m_kind == HJ_M_TANH) {
+  if constexpr (C::MK == HJ_M_TANH) {
     const T th = dtanh(r * P.inv_s);
     const T sech2 = T(1) - th * th;
     c = T(1) + P.kappa * th;
     c1 = P.kappa * P.inv_s * sech2;
     if (NEED2) c2 = T(-2) * P.kappa * P.inv_s * P.inv_s * th * sech2;
-  } else if (P.m_kind == HJ_M_RAT) {
+  } else {
     const T q = T(1) / (T(1) + r);
     c = T(1) + P.kappa * r * q;
     c1 = P.kappa * q * q;
     if (NEED2) c2 = T(-2) * P.kappa * q * q * q;
-  } else {
-    c = T(1);
-    c1 = T(0);
   }
   if (P.e == 2) {
     m = c * c;
@@ -159,41 +217,70 @@ __device__ __forceinline__ T integrand(const Problem<T>& P, T r, T q, T m, T m1)
 // (no drift).  NT independent trajectories are advanced together so their
 // instruction streams interleave.
 // ---------------------------------------------------------------------------
-template <typename T, int NPL, int LPT, int NT> struct Traj {
-  T g[NT][NPL], p[NT][NPL];
-};
 
-// r = |gamma|^2 and q = sum d p^2 at the stage state (G, Pp) for NT trajectories.
-template <typename T, int NPL, int LPT, int NT>
-__device__ __forceinline__ void reduce_rq(const T (&G)[NT][NPL], const T (&Pp)[NT][NPL],
-                                          const LaneParams<T, NPL>& L, T (&r)[NT], T (&q)[NT]) {
+// Sum of a[k] * b[k] over the lane's components as two interleaved FMA
+// chains (half the dependency depth of one chain, no extra instructions).
+template <int NPL, typename T>
+__device__ __forceinline__ T dot2(const T (&a)[NPL], const T (&b)[NPL]) {
+  T s0 = a[0] * b[0], s1 = T(0);
+#pragma unroll
+  for (int k = 1; k < NPL; ++k) {
+    if (k & 1)
+      s1 = __builtin_fma(a[k], b[k], s1);
+    else
+      s0 = __builtin_fma(a[k], b[k], s0);
+  }
+  return s0 + s1;
+}
+
+// r = |gamma|^2 and q = sum d p^2 at the stage state (G, Pp) for NT
+// trajectories, and the products dp = D p that the stage update reuses.
+template <class C, int NT>
+__device__ __forceinline__ void reduce_rq(const typename C::T (&G)[NT][C::NPL],
+                                          const typename C::T (&Pp)[NT][C::NPL],
+                                          const LaneParams<C>& L, typename C::T (&r)[NT],
+                                          typename C::T (&q)[NT],
+                                          typename C::T (&dp)[NT][C::NPL]) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    T rr = T(0), qq = T(0);
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      rr += G[t][k] * G[t][k];
-      qq += L.d[k] * Pp[t][k] * Pp[t][k];
-    }
-    r[t] = rr;
-    q[t] = qq;
+    for (int k = 0; k < C::NPL; ++k) dp[t][k] = L.d[k] * Pp[t][k];
+    r[t] = dot2<C::NPL>(G[t], G[t]);
+    q[t] = dot2<C::NPL>(dp[t], Pp[t]);
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    r[t] = gsum<LPT>(r[t]);
-    q[t] = gsum<LPT>(q[t]);
+    r[t] = gsum<C::LPT>(r[t]);
+    q[t] = gsum<C::LPT>(q[t]);
   }
+}
+template <class C, int NT>
+__device__ __forceinline__ void reduce_rq(const typename C::T (&G)[NT][C::NPL],
+                                          const typename C::T (&Pp)[NT][C::NPL],
+                                          const LaneParams<C>& L, typename C::T (&r)[NT],
+                                          typename C::T (&q)[NT]) {
+  typename C::T dp[NT][C::NPL];
+  reduce_rq<C, NT>(G, Pp, L, r, q, dp);
 }
 
 // One RK4 step y -> y_next for NT trajectories.  With QUAD the RK4-augmented
 // quadrature of the integrand is added into acc.  The y update is the same
 // instruction sequence with or without QUAD, which keeps the adjoint's
 // recomputation bit-identical to the forward solve.
-template <typename T, int NPL, int LPT, int NT, bool QUAD>
-__device__ __forceinline__ void rk4_step(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                         T (&g)[NT][NPL], T (&p)[NT][NPL], T (&acc)[NT]) {
+//
+// Stage s evaluates K = f(Y) = (-m D p, (q m' + w) gamma) and folds it into
+// the accumulator y + h/6 (K1 + 2 K2 + 2 K3 + K4) and the next stage state
+// Y' = y + c h K with scalar coefficients, so each component costs seven
+// FP64 operations per stage (D p, two reduction FMAs, four update FMAs).
+template <class C, int NT, bool QUAD>
+__device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const LaneParams<C>& L,
+                                         typename C::T (&g)[NT][C::NPL],
+                                         typename C::T (&p)[NT][C::NPL],
+                                         typename C::T (&acc)[NT]) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL;
   const T h = P.h, h2 = T(0.5) * P.h, h6 = P.h / T(6), h3 = P.h / T(3);
-  T G[NT][NPL], Pp[NT][NPL], ag[NT][NPL], ap[NT][NPL];
+  T G[NT][NPL], Pp[NT][NPL], ag[NT][NPL], ap[NT][NPL], dp[NT][NPL];
   T r[NT], q[NT], m[NT], m1[NT], m2[NT], ia[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -206,29 +293,24 @@ __device__ __forceinline__ void rk4_step(const Problem<T>& P, const LaneParams<T
   }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    reduce_rq<T, NPL, LPT, NT>(G, Pp, L, r, q);
+    reduce_rq<C, NT>(G, Pp, L, r, q, dp);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) speed<T, false>(P, r[t], m[t], m1[t], m2[t]);
+    for (int t = 0; t < NT; ++t) speed<C, false>(P, r[t], m[t], m1[t], m2[t]);
     const T wb = (s == 0 || s == 3) ? h6 : h3;  // RK4 weights h/6 (1, 2, 2, 1)
     const T cn = (s == 2) ? h : h2;             // next stage offset c_{s+1} h
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (QUAD) ia[t] += (s == 0 || s == 3 ? T(1) : T(2)) * integrand(P, r[t], q[t], m[t], m1[t]);
       const T cx = q[t] * m1[t] + P.w;
+      const T ag_c = -(wb * m[t]), ap_c = wb * cx;  // accumulator coefficients
+      const T gn_c = -(cn * m[t]), pn_c = cn * cx;  // next-stage coefficients
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
-        const T kg = -m[t] * (L.d[k] * Pp[t][k]);
-        const T kp = cx * G[t][k];
-        if (s == 0) {
-          ag[t][k] = g[t][k] + wb * kg;
-          ap[t][k] = p[t][k] + wb * kp;
-        } else {
-          ag[t][k] = ag[t][k] + wb * kg;
-          ap[t][k] = ap[t][k] + wb * kp;
-        }
+        ag[t][k] = __builtin_fma(ag_c, dp[t][k], s == 0 ? g[t][k] : ag[t][k]);
+        ap[t][k] = __builtin_fma(ap_c, G[t][k], s == 0 ? p[t][k] : ap[t][k]);
         if (s < 3) {
-          G[t][k] = g[t][k] + cn * kg;
-          Pp[t][k] = p[t][k] + cn * kp;
+          Pp[t][k] = __builtin_fma(pn_c, G[t][k], p[t][k]);
+          G[t][k] = __builtin_fma(gn_c, dp[t][k], g[t][k]);
         }
       }
     }
@@ -245,16 +327,19 @@ __device__ __forceinline__ void rk4_step(const Problem<T>& P, const LaneParams<T
 }
 
 // Integrand at a node (trapezoid rule).
-template <typename T, int NPL, int LPT, int NT>
-__device__ __forceinline__ void node_integrand(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                               const T (&g)[NT][NPL], const T (&p)[NT][NPL],
-                                               T (&out)[NT]) {
+template <class C, int NT>
+__device__ __forceinline__ void node_integrand(const Problem<typename C::T>& P,
+                                               const LaneParams<C>& L,
+                                               const typename C::T (&g)[NT][C::NPL],
+                                               const typename C::T (&p)[NT][C::NPL],
+                                               typename C::T (&out)[NT]) {
+  using T = typename C::T;
   T r[NT], q[NT];
-  reduce_rq<T, NPL, LPT, NT>(g, p, L, r, q);
+  reduce_rq<C, NT>(g, p, L, r, q);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     T m, m1, m2;
-    speed<T, false>(P, r[t], m, m1, m2);
+    speed<C, false>(P, r[t], m, m1, m2);
     out[t] = integrand(P, r[t], q[t], m, m1);
   }
 }
@@ -286,12 +371,17 @@ __device__ __forceinline__ void load_state(const T* base, size_t stride, size_t 
 // trajectories started at (x, v[t]); also the certificate residual rho and,
 // with STORE, the states y_{cK} (c = 0 .. ceil(N/K)-1) and y_N (slot
 // ceil(N/K)) for the adjoint of trajectory 0.
-template <typename T, int NPL, int LPT, int NT, bool STORE>
-__device__ __forceinline__ void forward(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                        const T (&x)[NPL], const T (&v)[NT][NPL], T (&phi)[NT],
-                                        T (&rho)[NT], T* ck = nullptr, size_t stride = 0,
+template <class C, int NT, bool STORE>
+__device__ __forceinline__ void forward(const Problem<typename C::T>& P, const LaneParams<C>& L,
+                                        const typename C::T (&x)[C::NPL],
+                                        const typename C::T (&v)[NT][C::NPL],
+                                        typename C::T (&phi)[NT], typename C::T (&rho)[NT],
+                                        typename C::T* ck = nullptr, size_t stride = 0,
                                         size_t lane = 0, int K = 1,
-                                        T (*yN_g)[NPL] = nullptr, T (*yN_p)[NPL] = nullptr) {
+                                        typename C::T (*yN_g)[C::NPL] = nullptr,
+                                        typename C::T (*yN_p)[C::NPL] = nullptr) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL, LPT = C::LPT;
   T g[NT][NPL], p[NT][NPL], acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -305,18 +395,18 @@ __device__ __forceinline__ void forward(const Problem<T>& P, const LaneParams<T,
   const bool aug = (P.quad == HJ_RK4AUG);
   if (!aug) {
     T io[NT];
-    node_integrand<T, NPL, LPT, NT>(P, L, g, p, io);
+    node_integrand<C, NT>(P, L, g, p, io);
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] += T(0.5) * P.h * io[t];
   }
   for (int s = 0; s < P.N; ++s) {
     if (STORE && (s % K) == 0) store_state<T, NPL>(ck, stride, lane, s / K, g[0], p[0]);
     if (aug) {
-      rk4_step<T, NPL, LPT, NT, true>(P, L, g, p, acc);
+      rk4_step<C, NT, true>(P, L, g, p, acc);
     } else {
-      rk4_step<T, NPL, LPT, NT, false>(P, L, g, p, acc);
+      rk4_step<C, NT, false>(P, L, g, p, acc);
       T io[NT];
-      node_integrand<T, NPL, LPT, NT>(P, L, g, p, io);
+      node_integrand<C, NT>(P, L, g, p, io);
       const T wk = (s + 1 < P.N) ? P.h : T(0.5) * P.h;
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] += wk * io[t];
@@ -365,20 +455,18 @@ template <typename T> struct StageScal {
   T r, q, m, m1, m2;
 };
 
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ StageScal<T> stage_scalars(const Problem<T>& P,
-                                                      const LaneParams<T, NPL>& L,
-                                                      const T (&G)[NPL], const T (&Pp)[NPL]) {
+template <class C>
+__device__ __forceinline__ StageScal<typename C::T> stage_scalars(
+    const Problem<typename C::T>& P, const LaneParams<C>& L, const typename C::T (&G)[C::NPL],
+    const typename C::T (&Pp)[C::NPL]) {
+  using T = typename C::T;
   StageScal<T> S;
-  T rr = T(0), qq = T(0);
+  T dp[C::NPL];
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
-    rr += G[k] * G[k];
-    qq += L.d[k] * Pp[k] * Pp[k];
-  }
-  S.r = gsum<LPT>(rr);
-  S.q = gsum<LPT>(qq);
-  speed<T, true>(P, S.r, S.m, S.m1, S.m2);
+  for (int k = 0; k < C::NPL; ++k) dp[k] = L.d[k] * Pp[k];
+  S.r = gsum<C::LPT>(dot2<C::NPL>(G, G));
+  S.q = gsum<C::LPT>(dot2<C::NPL>(dp, Pp));
+  speed<C, true>(P, S.r, S.m, S.m1, S.m2);
   return S;
 }
 
@@ -401,19 +489,20 @@ __device__ __forceinline__ void integrand_grad_coef(const Problem<T>& P, const S
 //               + (q m' + w) kp + wb cg gamma
 //   out_p     = D (-m kg + 2 m' <gamma, kp> p + wb cp p)
 // (kg, kp) is read from and out is written to the same arrays.
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ void vjp_stage(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                          const T (&G)[NPL], const T (&Pp)[NPL],
-                                          const StageScal<T>& S, T wb, T (&kg)[NPL],
-                                          T (&kp)[NPL]) {
-  T s1 = T(0), s2 = T(0);
+template <class C>
+__device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const LaneParams<C>& L,
+                                          const typename C::T (&G)[C::NPL],
+                                          const typename C::T (&Pp)[C::NPL],
+                                          const StageScal<typename C::T>& S, typename C::T wb,
+                                          typename C::T (&kg)[C::NPL],
+                                          typename C::T (&kp)[C::NPL]) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL;
+  T dp[NPL];
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
-    s1 += L.d[k] * Pp[k] * kg[k];
-    s2 += G[k] * kp[k];
-  }
-  s1 = gsum<LPT>(s1);
-  s2 = gsum<LPT>(s2);
+  for (int k = 0; k < NPL; ++k) dp[k] = L.d[k] * Pp[k];
+  const T s1 = gsum<C::LPT>(dot2<NPL>(dp, kg));
+  const T s2 = gsum<C::LPT>(dot2<NPL>(G, kp));
   T cg = T(0), cp = T(0);
   if (wb != T(0)) integrand_grad_coef(P, S, cg, cp);
   const T ag = T(-2) * S.m1 * s1 + T(2) * S.q * S.m2 * s2 + wb * cg;
@@ -421,8 +510,8 @@ __device__ __forceinline__ void vjp_stage(const Problem<T>& P, const LaneParams<
   const T ap = T(2) * S.m1 * s2 + wb * cp;
 #pragma unroll
   for (int k = 0; k < NPL; ++k) {
-    const T og = ag * G[k] + al * kp[k];
-    const T op = L.d[k] * (-S.m * kg[k] + ap * Pp[k]);
+    const T og = __builtin_fma(al, kp[k], ag * G[k]);
+    const T op = __builtin_fma(ap, dp[k], -S.m * (L.d[k] * kg[k]));
     kg[k] = og;
     kp[k] = op;
   }
@@ -430,32 +519,32 @@ __device__ __forceinline__ void vjp_stage(const Problem<T>& P, const LaneParams<
 
 // Reverse sweep through one RK4 step from y_k = (g, p): lam holds d(obj)/d
 // y_{k+1} on entry and d(obj)/d y_k on exit (stage recomputation in registers).
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ void reverse_step(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                             const T (&g)[NPL], const T (&p)[NPL], bool aug,
-                                             T (&lg)[NPL], T (&lp)[NPL]) {
+template <class C>
+__device__ __forceinline__ void reverse_step(const Problem<typename C::T>& P,
+                                             const LaneParams<C>& L,
+                                             const typename C::T (&g)[C::NPL],
+                                             const typename C::T (&p)[C::NPL], bool aug,
+                                             typename C::T (&lg)[C::NPL],
+                                             typename C::T (&lp)[C::NPL]) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL;
   const T h = P.h, h2 = T(0.5) * P.h, h6 = P.h / T(6), h3 = P.h / T(3);
-  T YG[4][NPL], YP[4][NPL];
+  T YG[3][NPL], YP[3][NPL];  // stage states 2..4 (stage 1 is y_k itself)
   StageScal<T> S[4];
+  S[0] = stage_scalars<C>(P, L, g, p);
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
-    YG[0][k] = g[k];
-    YP[0][k] = p[k];
-  }
+  for (int s = 0; s < 3; ++s) {
+    const T cn = (s == 2) ? h : h2;
+    const T cx = S[s].q * S[s].m1 + P.w;
+    const T gn_c = -(cn * S[s].m), pn_c = cn * cx;  // as in rk4_step
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    S[s] = stage_scalars<T, NPL, LPT>(P, L, YG[s], YP[s]);
-    if (s < 3) {
-      const T cn = (s == 2) ? h : h2;
-      const T cx = S[s].q * S[s].m1 + P.w;
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) {
-        const T kg = -S[s].m * (L.d[k] * YP[s][k]);
-        const T kp = cx * YG[s][k];
-        YG[s + 1][k] = g[k] + cn * kg;
-        YP[s + 1][k] = p[k] + cn * kp;
-      }
+    for (int k = 0; k < NPL; ++k) {
+      const T gs = s ? YG[s - 1][k] : g[k];
+      const T ps = s ? YP[s - 1][k] : p[k];
+      YG[s][k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+      YP[s][k] = __builtin_fma(pn_c, gs, p[k]);
     }
+    S[s + 1] = stage_scalars<C>(P, L, YG[s], YP[s]);
   }
   // ybar accumulates d/dy_k; bg/bp carries Ybar of the stage above.
   T yg[NPL], yp[NPL], bg[NPL], bp[NPL];
@@ -478,7 +567,10 @@ __device__ __forceinline__ void reverse_step(const Problem<T>& P, const LanePara
         bp[k] = wb * lp[k] + cn * bp[k];
       }
     }
-    vjp_stage<T, NPL, LPT>(P, L, YG[s], YP[s], S[s], aug ? wb : T(0), bg, bp);
+    if (s == 0)
+      vjp_stage<C>(P, L, g, p, S[0], aug ? wb : T(0), bg, bp);
+    else
+      vjp_stage<C>(P, L, YG[s - 1], YP[s - 1], S[s], aug ? wb : T(0), bg, bp);
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       yg[k] += bg[k];
@@ -493,15 +585,19 @@ __device__ __forceinline__ void reverse_step(const Problem<T>& P, const LanePara
 }
 
 // lam += wk * grad(integrand)(y)   (trapezoid node term)
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ void add_node_grad(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                              const T (&g)[NPL], const T (&p)[NPL], T wk,
-                                              T (&lg)[NPL], T (&lp)[NPL]) {
-  const StageScal<T> S = stage_scalars<T, NPL, LPT>(P, L, g, p);
+template <class C>
+__device__ __forceinline__ void add_node_grad(const Problem<typename C::T>& P,
+                                              const LaneParams<C>& L,
+                                              const typename C::T (&g)[C::NPL],
+                                              const typename C::T (&p)[C::NPL], typename C::T wk,
+                                              typename C::T (&lg)[C::NPL],
+                                              typename C::T (&lp)[C::NPL]) {
+  using T = typename C::T;
+  const StageScal<T> S = stage_scalars<C>(P, L, g, p);
   T cg, cp;
   integrand_grad_coef(P, S, cg, cp);
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
+  for (int k = 0; k < C::NPL; ++k) {
     lg[k] += wk * cg * g[k];
     lp[k] += wk * cp * L.d[k] * p[k];
   }
@@ -509,11 +605,16 @@ __device__ __forceinline__ void add_node_grad(const Problem<T>& P, const LanePar
 
 // Gradient of the objective w.r.t. (x, v) from the checkpoints written by
 // forward<STORE>.  seg is per-lane scratch for K states.
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ void backward(const Problem<T>& P, const LaneParams<T, NPL>& L,
-                                         const T (&x)[NPL], const T (&v)[NPL], const T* ck,
-                                         T* seg, size_t stride, size_t lane, int K,
-                                         T (&gv)[NPL], T (&gx)[NPL]) {
+template <class C>
+__device__ __forceinline__ void backward(const Problem<typename C::T>& P, const LaneParams<C>& L,
+                                         const typename C::T (&x)[C::NPL],
+                                         const typename C::T (&v)[C::NPL],
+                                         const typename C::T* ck, typename C::T* seg,
+                                         size_t stride, size_t lane, int K,
+                                         typename C::T (&gv)[C::NPL],
+                                         typename C::T (&gx)[C::NPL]) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL;
   const bool aug = (P.quad == HJ_RK4AUG);
   const int nseg = (P.N + K - 1) / K;
   T lg[NPL], lp[NPL], g[NPL], p[NPL];
@@ -528,7 +629,7 @@ __device__ __forceinline__ void backward(const Problem<T>& P, const LaneParams<T
       lp[k] = L.a2[k] * p[k];
     }
   }
-  if (!aug) add_node_grad<T, NPL, LPT>(P, L, g, p, T(0.5) * P.h, lg, lp);
+  if (!aug) add_node_grad<C>(P, L, g, p, T(0.5) * P.h, lg, lp);
   for (int c = nseg - 1; c >= 0; --c) {
     const int k0 = c * K;
     const int k1 = (k0 + K < P.N) ? k0 + K : P.N;
@@ -541,7 +642,7 @@ __device__ __forceinline__ void backward(const Problem<T>& P, const LaneParams<T
         gg[0][k] = g[k];
         pp[0][k] = p[k];
       }
-      rk4_step<T, NPL, LPT, 1, false>(P, L, gg, pp, dummy);
+      rk4_step<C, 1, false>(P, L, gg, pp, dummy);
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         g[k] = gg[0][k];
@@ -554,8 +655,8 @@ __device__ __forceinline__ void backward(const Problem<T>& P, const LaneParams<T
         load_state<T, NPL>(ck, stride, lane, c, g, p);
       else
         load_state<T, NPL>(seg, stride, lane, j - k0, g, p);
-      reverse_step<T, NPL, LPT>(P, L, g, p, aug, lg, lp);
-      if (!aug) add_node_grad<T, NPL, LPT>(P, L, g, p, j == 0 ? T(0.5) * P.h : P.h, lg, lp);
+      reverse_step<C>(P, L, g, p, aug, lg, lp);
+      if (!aug) add_node_grad<C>(P, L, g, p, j == 0 ? T(0.5) * P.h : P.h, lg, lp);
     }
   }
 #pragma unroll

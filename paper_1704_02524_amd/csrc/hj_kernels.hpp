@@ -1,59 +1,16 @@
 // hj_kernels.hpp -- the solver kernels: objective evaluation (with optional
 // exact gradient), central-difference coordinate descent, adjoint gradient
-// descent, and per-point selection over the guess slots.
+// descent, and per-point selection over the guess slots.  Each kernel is a
+// template over a Cfg (arithmetic type, components per lane, lanes per task,
+// speed profile); hj_inst_*.hip instantiate them and hj_api.hip dispatches.
 #pragma once
 
 #include "hj_device.hpp"
+#include "hj_launch.hpp"
 
 namespace hj {
 
-// Per-slot result records (device arrays [B*G], v in [B*G, n]).
-template <typename T> struct SlotOut {
-  double* phi;
-  double* rho;
-  int32_t* status;
-  int32_t* cert;
-  int32_t* iters;
-  int32_t* attempts;
-  int64_t* n_fwd;
-  int64_t* n_bwd;
-  T* v;
-};
-
-template <typename T> struct SolveArgs {
-  Problem<T> P;
-  Problem<double> P64;  // the same problem in FP64 (certificate of FP32 runs)
-  const T* x;           // [B, n]
-  const T* guesses;     // [B, G, R+1, n]
-  int64_t B;
-  int G, R;
-  int max_iter, K;
-  int cert_fp64;
-  T alpha0, sigma, eps_step, acc_rel, armijo_c, v_max;
-  double cert_tol;
-  T* ck;                // adjoint checkpoints, SoA over `stride` lanes
-  T* seg;               // adjoint segment scratch
-  size_t stride;
-  SlotOut<T> out;
-};
-
-template <typename T> struct EvalArgs {
-  Problem<T> P;
-  const T* x;   // [B, n]
-  const T* v;   // [B, G, n]
-  int64_t B;
-  int G, K;
-  double* phi;  // [B, G]
-  double* rho;  // [B, G] or null
-  T* yN;        // [B, G, 2n] or null
-  T* gv;        // [B, G, n] or null
-  T* gx;        // [B, G, n] or null
-  T* ck;
-  T* seg;
-  size_t stride;
-};
-
-// load n-vector row `row` into the lane's NPL components (0 beyond n)
+// load n-vector row into the lane's NPL components (0 beyond n)
 template <typename T, int NPL>
 __device__ __forceinline__ void load_row(const T* base, int n, int sub, T (&out)[NPL]) {
 #pragma unroll
@@ -74,24 +31,26 @@ __device__ __forceinline__ void store_row(T* base, int n, int sub, const T (&in)
 // ---------------------------------------------------------------------------
 // objective evaluation (and exact gradient)
 // ---------------------------------------------------------------------------
-template <typename T, int NPL, int LPT>
-__global__ __launch_bounds__(256) void k_eval(EvalArgs<T> A) {
+template <class C>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C::T> A) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL, LPT = C::LPT;
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = threadIdx.x % LPT;
   const int64_t task = (int64_t)(lane / LPT);
   if (task >= A.B * A.G) return;
   const int64_t b = task / A.G;
   const int n = A.P.n;
-  LaneParams<T, NPL> L;
+  LaneParams<C> L;
   L.load(A.P, sub);
   T x[NPL], v[1][NPL], phi[1], rho[1], yg[1][NPL], yp[1][NPL];
   load_row<T, NPL>(A.x + b * n, n, sub, x);
   load_row<T, NPL>(A.v + task * n, n, sub, v[0]);
   const bool grad = (A.gv != nullptr) || (A.gx != nullptr);
   if (grad)
-    forward<T, NPL, LPT, 1, true>(A.P, L, x, v, phi, rho, A.ck, A.stride, lane, A.K, yg, yp);
+    forward<C, 1, true>(A.P, L, x, v, phi, rho, A.ck, A.stride, lane, A.K, yg, yp);
   else
-    forward<T, NPL, LPT, 1, false>(A.P, L, x, v, phi, rho, nullptr, 0, 0, 1, yg, yp);
+    forward<C, 1, false>(A.P, L, x, v, phi, rho, nullptr, 0, 0, 1, yg, yp);
   if (sub == 0) {
     A.phi[task] = (double)phi[0];
     if (A.rho) A.rho[task] = (double)rho[0];
@@ -102,7 +61,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> A) {
   }
   if (grad) {
     T gv[NPL], gx[NPL];
-    backward<T, NPL, LPT>(A.P, L, x, v[0], A.ck, A.seg, A.stride, lane, A.K, gv, gx);
+    backward<C>(A.P, L, x, v[0], A.ck, A.seg, A.stride, lane, A.K, gv, gx);
     if (A.gv) store_row<T, NPL>(A.gv + task * n, n, sub, gv);
     if (A.gx) store_row<T, NPL>(A.gx + task * n, n, sub, gx);
   }
@@ -111,7 +70,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<T> A) {
 // ---------------------------------------------------------------------------
 // shared per-slot bookkeeping
 // ---------------------------------------------------------------------------
-template <typename T> struct SlotBest {
+struct SlotBest {
   double phi = __builtin_nan(""), rho = __builtin_nan("");
   int32_t cert = -1, status = HJ_ST_DIVERGED, iters = 0, attempts = 0;
   int64_t n_fwd = 0, n_bwd = 0;
@@ -119,39 +78,46 @@ template <typename T> struct SlotBest {
 
 // Certificate and objective of a finished run, in FP64.  FP32 runs with the
 // FP64 certificate re-solve the characteristic in FP64 at the final v.
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ void final_values(const SolveArgs<T>& A, int sub, const T (&x)[NPL],
-                                             const T (&v)[NPL], T phi, T rho, double& phi64,
-                                             double& rho64) {
-  if (sizeof(T) == 4 && A.cert_fp64) {
-    LaneParams<double, NPL> L64;
-    L64.load(A.P64, sub);
-    double x64[NPL], v64[1][NPL], ph[1], rh[1];
+template <class C>
+__device__ __forceinline__ void final_values(const SolveArgs<typename C::T>& A, int sub,
+                                             const typename C::T (&x)[C::NPL],
+                                             const typename C::T (&v)[C::NPL],
+                                             typename C::T phi, typename C::T rho,
+                                             double& phi64, double& rho64) {
+  if constexpr (sizeof(typename C::T) == 4) {
+    if (A.cert_fp64) {
+      using C64 = Cfg<double, C::NPL, C::LPT, C::MK>;
+      LaneParams<C64> L64;
+      L64.load(A.P64, sub);
+      double x64[C::NPL], v64[1][C::NPL], ph[1], rh[1];
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      x64[k] = (double)x[k];
-      v64[0][k] = (double)v[k];
+      for (int k = 0; k < C::NPL; ++k) {
+        x64[k] = (double)x[k];
+        v64[0][k] = (double)v[k];
+      }
+      forward<C64, 1, false>(A.P64, L64, x64, v64, ph, rh);
+      phi64 = ph[0];
+      rho64 = rh[0];
+      return;
     }
-    forward<double, NPL, LPT, 1, false>(A.P64, L64, x64, v64, ph, rh);
-    phi64 = ph[0];
-    rho64 = rh[0];
-  } else {
-    phi64 = (double)phi;
-    rho64 = (double)rho;
   }
+  phi64 = (double)phi;
+  rho64 = (double)rho;
 }
 
 // Record the end of one attempt; returns true when the slot is finished.
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ bool end_attempt(const SolveArgs<T>& A, int sub, int64_t task,
-                                            const T (&x)[NPL], const T (&v)[NPL], T phi, T rho,
-                                            int status, int it, int att, SlotBest<T>& best) {
+template <class C>
+__device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A, int sub,
+                                            int64_t task, const typename C::T (&x)[C::NPL],
+                                            const typename C::T (&v)[C::NPL], typename C::T phi,
+                                            typename C::T rho, int status, int it, int att,
+                                            SlotBest& best) {
   double phi64, rho64;
   if (status == HJ_ST_DIVERGED) {
     phi64 = (double)phi;
     rho64 = __builtin_nan("");
   } else {
-    final_values<T, NPL, LPT>(A, sub, x, v, phi, rho, phi64, rho64);
+    final_values<C>(A, sub, x, v, phi, rho, phi64, rho64);
   }
   best.iters += it;
   best.attempts = att + 1;
@@ -162,19 +128,20 @@ __device__ __forceinline__ bool end_attempt(const SolveArgs<T>& A, int sub, int6
     best.rho = rho64;
     best.cert = certified ? 1 : 0;
     best.status = status;
-    store_row<T, NPL>(A.out.v + task * A.P.n, A.P.n, sub, v);
+    store_row<typename C::T, C::NPL>(A.out.v + task * A.P.n, A.P.n, sub, v);
   }
   return certified || (att + 1 > A.R);
 }
 
-template <typename T, int NPL, int LPT>
-__device__ __forceinline__ void write_slot(const SolveArgs<T>& A, int sub, int64_t task,
-                                           const SlotBest<T>& best) {
+template <class C>
+__device__ __forceinline__ void write_slot(const SolveArgs<typename C::T>& A, int sub,
+                                           int64_t task, const SlotBest& best) {
+  using T = typename C::T;
   if (best.cert < 0) {
-    T nanv[NPL];
+    T nanv[C::NPL];
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) nanv[k] = T(__builtin_nan(""));
-    store_row<T, NPL>(A.out.v + task * A.P.n, A.P.n, sub, nanv);
+    for (int k = 0; k < C::NPL; ++k) nanv[k] = T(__builtin_nan(""));
+    store_row<T, C::NPL>(A.out.v + task * A.P.n, A.P.n, sub, nanv);
   }
   if (sub != 0) return;
   if (A.out.phi) A.out.phi[task] = best.phi;
@@ -195,26 +162,47 @@ __device__ __forceinline__ bool accept_step(const SolveArgs<T>& A, T trial, T cu
   return trial <= cur - A.armijo_c * decrease + A.acc_rel * dabs(cur);
 }
 
+// Stop tests at the end of an iteration, in the order of the reference.
+template <class C>
+__device__ __forceinline__ int stop_status(const SolveArgs<typename C::T>& A,
+                                           const typename C::T (&v)[C::NPL],
+                                           typename C::T phi, typename C::T smax,
+                                           typename C::T alpha, int it) {
+  using T = typename C::T;
+  const T alpha_floor = A.alpha0 * T(9.094947017729282e-13);  // alpha0 * 2^-40
+  T vmax = T(0);
+#pragma unroll
+  for (int k = 0; k < C::NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
+  vmax = gmax<C::LPT>(vmax);
+  if (!isfinite(phi) || !(vmax <= A.v_max)) return HJ_ST_DIVERGED;
+  if (smax < A.eps_step) return HJ_ST_CONVERGED;
+  if (alpha < alpha_floor) return HJ_ST_STALLED;
+  if (it >= A.max_iter) return HJ_ST_MAXITER;
+  return -1;
+}
+
 // ---------------------------------------------------------------------------
 // cyclic coordinate descent with central differences (Algorithm 1; one
-// iteration = one sweep over the n coordinates; the step halves on ascent)
+// iteration = one sweep over the n coordinates; the step halves when a trial
+// fails the step test)
 // ---------------------------------------------------------------------------
-template <typename T, int NPL, int LPT>
-__global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<T> A) {
+template <class C>
+__global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL, LPT = C::LPT;
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = threadIdx.x % LPT;
   const int64_t task = (int64_t)(lane / LPT);
   if (task >= A.B * A.G) return;
   const int64_t b = task / A.G;
   const int n = A.P.n;
-  LaneParams<T, NPL> L;
+  LaneParams<C> L;
   L.load(A.P, sub);
   T x[NPL], v[NPL];
   load_row<T, NPL>(A.x + b * n, n, sub, x);
   const T* g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
   load_row<T, NPL>(g0, n, sub, v);
-  SlotBest<T> best;
-  const T alpha_floor = A.alpha0 * T(9.094947017729282e-13);  // alpha0 * 2^-40
+  SlotBest best;
   int att = 0, it = 0, j = 0;
   bool start = true;
   T alpha = A.alpha0, phi = T(0), rho = T(0), smax = T(0);
@@ -227,7 +215,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<T> A) {
       va[0][k] = on ? v[k] + A.sigma : v[k];
       va[1][k] = on ? v[k] - A.sigma : v[k];
     }
-    forward<T, NPL, LPT, 2, false>(A.P, L, x, va, fp, rp);
+    forward<C, 2, false>(A.P, L, x, va, fp, rp);
     int status = -1;
     if (start) {
       best.n_fwd += 1;
@@ -249,7 +237,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<T> A) {
       T vt[1][NPL], ft[1], rt[1];
 #pragma unroll
       for (int k = 0; k < NPL; ++k) vt[0][k] = (sub * NPL + k == j) ? v[k] - step : v[k];
-      forward<T, NPL, LPT, 1, false>(A.P, L, x, vt, ft, rt);
+      forward<C, 1, false>(A.P, L, x, vt, ft, rt);
       best.n_fwd += 3;
       if (accept_step(A, ft[0], phi, alpha * gj * gj)) {
 #pragma unroll
@@ -262,43 +250,34 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<T> A) {
       if (++j == n) {
         j = 0;
         ++it;
-        T vmax = T(0);
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
-        vmax = gmax<LPT>(vmax);
-        if (!isfinite(phi) || !(vmax <= A.v_max))
-          status = HJ_ST_DIVERGED;
-        else if (smax < A.eps_step)
-          status = HJ_ST_CONVERGED;
-        else if (alpha < alpha_floor)
-          status = HJ_ST_STALLED;
-        else if (it >= A.max_iter)
-          status = HJ_ST_MAXITER;
+        status = stop_status<C>(A, v, phi, smax, alpha, it);
         smax = T(0);
       }
     }
     if (status >= 0) {
-      if (end_attempt<T, NPL, LPT>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
+      if (end_attempt<C>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
       ++att;
       load_row<T, NPL>(g0 + (int64_t)att * n, n, sub, v);
       start = true;
     }
   }
-  write_slot<T, NPL, LPT>(A, sub, task, best);
+  write_slot<C>(A, sub, task, best);
 }
 
 // ---------------------------------------------------------------------------
 // gradient descent with the exact discrete gradient (adjoint + checkpoints)
 // ---------------------------------------------------------------------------
-template <typename T, int NPL, int LPT>
-__global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<T> A) {
+template <class C>
+__global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL, LPT = C::LPT;
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = threadIdx.x % LPT;
   const int64_t task = (int64_t)(lane / LPT);
   if (task >= A.B * A.G) return;
   const int64_t b = task / A.G;
   const int n = A.P.n;
-  LaneParams<T, NPL> L;
+  LaneParams<C> L;
   L.load(A.P, sub);
   T x[NPL], v[NPL], g[NPL];
   load_row<T, NPL>(A.x + b * n, n, sub, x);
@@ -306,8 +285,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<T> A) {
   load_row<T, NPL>(g0, n, sub, v);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) g[k] = T(0);
-  SlotBest<T> best;
-  const T alpha_floor = A.alpha0 * T(9.094947017729282e-13);  // alpha0 * 2^-40
+  SlotBest best;
   int att = 0, it = 0;
   bool start = true;
   T alpha = A.alpha0, phi = T(0), rho = T(0);
@@ -318,17 +296,17 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<T> A) {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) vt[0][k] = v[k];
     } else {
-      T gm = T(0);
+      T gm = T(0), g2[NPL];
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         gm = nanmax(gm, dabs(g[k]));
-        gg += g[k] * g[k];
+        g2[k] = g[k] * g[k];
         vt[0][k] = v[k] - alpha * g[k];
       }
       smax = alpha * gmax<LPT>(gm);
-      gg = gsum<LPT>(gg);
+      gg = gsum<LPT>(tree_sum<NPL>(g2));
     }
-    forward<T, NPL, LPT, 1, true>(A.P, L, x, vt, ft, rt, A.ck, A.stride, lane, A.K);
+    forward<C, 1, true>(A.P, L, x, vt, ft, rt, A.ck, A.stride, lane, A.K);
     best.n_fwd += 1;
     const bool acc = start || accept_step(A, ft[0], phi, alpha * gg);
     if (acc) {
@@ -341,7 +319,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<T> A) {
     }
     if (acc && isfinite(phi)) {
       T gx[NPL];
-      backward<T, NPL, LPT>(A.P, L, x, v, A.ck, A.seg, A.stride, lane, A.K, g, gx);
+      backward<C>(A.P, L, x, v, A.ck, A.seg, A.stride, lane, A.K, g, gx);
       best.n_bwd += 1;
     }
     int status = -1;
@@ -355,27 +333,16 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<T> A) {
         status = HJ_ST_MAXITER;
     } else {
       ++it;
-      T vmax = T(0);
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
-      vmax = gmax<LPT>(vmax);
-      if (!isfinite(phi) || !(vmax <= A.v_max))
-        status = HJ_ST_DIVERGED;
-      else if (smax < A.eps_step)
-        status = HJ_ST_CONVERGED;
-      else if (alpha < alpha_floor)
-        status = HJ_ST_STALLED;
-      else if (it >= A.max_iter)
-        status = HJ_ST_MAXITER;
+      status = stop_status<C>(A, v, phi, smax, alpha, it);
     }
     if (status >= 0) {
-      if (end_attempt<T, NPL, LPT>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
+      if (end_attempt<C>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
       ++att;
       load_row<T, NPL>(g0 + (int64_t)att * n, n, sub, v);
       start = true;
     }
   }
-  write_slot<T, NPL, LPT>(A, sub, task, best);
+  write_slot<C>(A, sub, task, best);
 }
 
 // ---------------------------------------------------------------------------
@@ -411,4 +378,49 @@ __global__ __launch_bounds__(256) void k_select(int64_t B, int G, int n, int for
   }
 }
 
+// ---------------------------------------------------------------------------
+// launchers (explicitly instantiated in hj_inst_*.hip)
+// ---------------------------------------------------------------------------
+template <class C>
+hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, hipStream_t st) {
+  const int64_t threads = A.B * A.G * C::LPT;
+  const int block = 256;
+  const int64_t grid = (threads + block - 1) / block;
+  if (mode == HJ_CD_FD)
+    hipLaunchKernelGGL(k_solve_cd<C>, dim3((unsigned)grid), dim3(block), 0, st, A);
+  else
+    hipLaunchKernelGGL(k_solve_gd<C>, dim3((unsigned)grid), dim3(block), 0, st, A);
+  return hipGetLastError();
+}
+
+template <class C>
+hipError_t launch_eval(const EvalArgs<typename C::T>& A, hipStream_t st) {
+  const int64_t threads = A.B * A.G * C::LPT;
+  const int block = 256;
+  const int64_t grid = (threads + block - 1) / block;
+  hipLaunchKernelGGL(k_eval<C>, dim3((unsigned)grid), dim3(block), 0, st, A);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_select(int64_t B, int G, int n, int formula, const double* s_phi,
+                         const int32_t* s_cert, const T* s_v, double* out_u, T* out_arg,
+                         int32_t* out_cert, hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (B + block - 1) / block;
+  hipLaunchKernelGGL(k_select<T>, dim3((unsigned)grid), dim3(block), 0, st, B, G, n, formula,
+                     s_phi, s_cert, s_v, out_u, out_arg, out_cert);
+  return hipGetLastError();
+}
+
 }  // namespace hj
+
+// Explicit instantiation of the launchers of one Cfg.
+#define HJ_INSTANTIATE(T, NPL, LPT, MK)                                                     \
+  template hipError_t hj::launch_solve<hj::Cfg<T, NPL, LPT, MK>>(const hj::SolveArgs<T>&,  \
+                                                                 int, hipStream_t);         \
+  template hipError_t hj::launch_eval<hj::Cfg<T, NPL, LPT, MK>>(const hj::EvalArgs<T>&,    \
+                                                                hipStream_t);
+#define HJ_INSTANTIATE_BOTH(T, NPL, LPT) \
+  HJ_INSTANTIATE(T, NPL, LPT, HJ_M_TANH) \
+  HJ_INSTANTIATE(T, NPL, LPT, HJ_M_RAT)

@@ -1,0 +1,85 @@
+// hj_launch.hpp -- kernel argument blocks, launcher declarations and the
+// table of compiled lane shapes, shared by the host dispatch (hj_api.hip) and
+// the instantiation units (hj_inst_*.hip).
+#pragma once
+
+#include "hj_device.hpp"
+
+namespace hj {
+
+// Per-slot result records (device arrays [B*G], v in [B*G, n]).
+template <typename T> struct SlotOut {
+  double* phi;
+  double* rho;
+  int32_t* status;
+  int32_t* cert;
+  int32_t* iters;
+  int32_t* attempts;
+  int64_t* n_fwd;
+  int64_t* n_bwd;
+  T* v;
+};
+
+template <typename T> struct SolveArgs {
+  Problem<T> P;
+  Problem<double> P64;  // the same problem in FP64 (certificate of FP32 runs)
+  const T* x;           // [B, n]
+  const T* guesses;     // [B, G, R+1, n]
+  int64_t B;
+  int G, R;
+  int max_iter, K;
+  int cert_fp64;
+  T alpha0, sigma, eps_step, acc_rel, armijo_c, v_max;
+  double cert_tol;
+  T* ck;                // adjoint checkpoints, SoA over `stride` lanes
+  T* seg;               // adjoint segment scratch
+  size_t stride;
+  SlotOut<T> out;
+};
+
+template <typename T> struct EvalArgs {
+  Problem<T> P;
+  const T* x;   // [B, n]
+  const T* v;   // [B, G, n]
+  int64_t B;
+  int G, K;
+  double* phi;  // [B, G]
+  double* rho;  // [B, G] or null
+  T* yN;        // [B, G, 2n] or null
+  T* gv;        // [B, G, n] or null
+  T* gx;        // [B, G, n] or null
+  T* ck;
+  T* seg;
+  size_t stride;
+};
+
+template <class C>
+hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, hipStream_t st);
+template <class C>
+hipError_t launch_eval(const EvalArgs<typename C::T>& A, hipStream_t st);
+template <typename T>
+hipError_t launch_select(int64_t B, int G, int n, int formula, const double* s_phi,
+                         const int32_t* s_cert, const T* s_v, double* out_u, T* out_arg,
+                         int32_t* out_cert, hipStream_t st);
+
+// Lane shapes compiled for both arithmetic types and both speed profiles
+// (components per lane NPL x lanes per task LPT), in order of preference
+// for a given n when no shape is requested: the first entry whose NPL * LPT
+// covers n.
+struct Shape {
+  int npl, lpt;
+  constexpr int npad() const { return npl * lpt; }
+};
+constexpr Shape kShapes[] = {
+    {2, 1}, {4, 1}, {4, 2}, {5, 2}, {3, 4}, {4, 4}, {8, 4}, {8, 8}, {13, 8}, {16, 8},
+    // alternatives reachable through an explicit lanes-per-task request
+    {2, 2}, {8, 1}, {2, 4}, {10, 1}, {8, 2}, {4, 8}, {7, 16},
+};
+constexpr int kNumDefaultShapes = 10;
+
+}  // namespace hj
+
+// X-macro over the shape table, for instantiation and dispatch.
+#define HJ_FOR_EACH_SHAPE(X) \
+  X(2, 1) X(4, 1) X(4, 2) X(5, 2) X(3, 4) X(4, 4) X(8, 4) X(8, 8) X(13, 8) X(16, 8) \
+  X(2, 2) X(8, 1) X(2, 4) X(10, 1) X(8, 2) X(4, 8) X(7, 16)

@@ -41,7 +41,7 @@ class Guesses(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("formula", C.c_int32), ("mode", C.c_int32),
                 ("quad", C.c_int32), ("max_iter", C.c_int32), ("ckpt_K", C.c_int32),
-                ("cert_fp64", C.c_int32), ("reserved", C.c_int32),
+                ("cert_fp64", C.c_int32), ("lanes_per_task", C.c_int32),
                 ("alpha0", C.c_double), ("fd_sigma", C.c_double), ("eps_step", C.c_double),
                 ("cert_tol", C.c_double), ("v_max", C.c_double), ("acc_rel", C.c_double),
                 ("armijo_c", C.c_double),

@@ -101,6 +101,41 @@ def test_eval_matches_reference_fp32(hj, n):
                                        atol=1e-3 * max(1.0, np.abs(gv).max()))
 
 
+@pytest.mark.parametrize("n,lpts,dtype", [(10, [1, 2, 4], W.F64), (3, [1, 2, 4], W.F64),
+                                          (32, [4, 8], W.F64), (100, [8, 16], W.F32)])
+def test_lane_shapes_agree_with_reference(hj, n, lpts, dtype):
+    """Every compiled lane shape (components per lane x lanes per task) gives
+    the reference's objective and gradient."""
+    wl = _family(n, W.HOPF, W.M_TANH, 1, W.RK4AUG, signs=True, B=3, G=2, dtype=dtype)
+    v = wl.guesses[:, :, 0, :].copy()
+    o = Oracle.from_workload(wl)
+    tol = 1e-12 if dtype == W.F64 else 1e-4
+    for lpt in lpts:
+        out = hj.evaluate(wl, _dev(wl.x, wl), _dev(v, wl), grad=True, lanes_per_task=lpt)
+        torch.cuda.synchronize()
+        for b in range(3):
+            for g in range(2):
+                phi, _ = o.eval(wl.x[b], v[b, g])
+                _, gv, _ = o.grad_tangent(wl.x[b], v[b, g])
+                assert abs(out["phi"][b, g].item() - phi) <= tol * max(1.0, abs(phi)), lpt
+                np.testing.assert_allclose(out["grad_v"][b, g].cpu().numpy(), gv, rtol=0,
+                                           atol=100 * tol * max(1.0, np.abs(gv).max()))
+
+
+def test_solve_shapes_agree(hj):
+    wl = W.c1_hopf_n10(B=64)
+    x, g = hj.device_inputs(wl)
+    ref = None
+    for lpt in [1, 2, 4]:
+        res = hj.solve(wl, x, g, lanes_per_task=lpt)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = {k: v.cpu().numpy() for k, v in res.items()}
+            continue
+        np.testing.assert_array_equal(res["cert"].cpu().numpy(), ref["cert"])
+        np.testing.assert_allclose(res["u"].cpu().numpy(), ref["u"], rtol=1e-10, atol=1e-10)
+
+
 def test_checkpoint_interval_does_not_change_the_gradient(hj):
     wl = _family(10, W.HOPF, W.M_TANH, 1, W.RK4AUG, signs=True, nsteps=37)
     x, v = _dev(wl.x, wl), _dev(wl.guesses[:, :, 0, :].copy(), wl)
