@@ -130,7 +130,17 @@ typedef struct {
     void   *ev_begin;     /* optional hipEvent_t recorded on the stream just
                              before the descent (or evaluation) kernel     */
     void   *ev_end;       /* optional hipEvent_t recorded just after it    */
+    int32_t schedule;     /* HJ_SCHED_*: how (point, guess) tasks reach the
+                             lanes                                          */
+    int32_t reserved2;
 } hj_opts;
+
+enum {
+    HJ_SCHED_AUTO = 0,       /* persistent when tasks outnumber resident lanes */
+    HJ_SCHED_STATIC = 1,     /* one task per lane group                       */
+    HJ_SCHED_PERSISTENT = 2  /* resident lane groups pop tasks from a queue;
+                                scratch is sized by resident lanes only      */
+};
 
 /* Optional per-slot outputs, device pointers, each NULL or [B, G] (v_final
  * [B, G, n] in dtype).  A slot's reported attempt is its first certified
@@ -181,6 +191,49 @@ int32_t hj_eval(int32_t H_kind, const hj_h_params *H, int32_t J_kind, const hj_j
                 const void *v, int32_t G, const hj_opts *opts,
                 double *out_phi, void *out_yN, double *out_rho,
                 void *out_grad_v, void *out_grad_x);
+
+/* One problem instance of a batched solve (all device arrays as in
+ * hj_solve; H and J parameter arrays are host pointers copied at planning). */
+typedef struct {
+    int32_t      n;
+    double       t;
+    int32_t      nsteps;
+    hj_h_params  H;
+    hj_j_params  J;
+    const void  *x;           /* device dtype [B, n]                        */
+    int64_t      B;
+    hj_guesses   guesses;     /* G, R_max, device init [B, G, R_max+1, n]  */
+    double      *out_u;       /* device [B]                                 */
+    void        *out_argopt;  /* device dtype [B, n]                        */
+    int32_t     *out_cert;    /* device [B]                                 */
+    hj_slot_diag diag;        /* optional per-slot outputs (NULL members)   */
+} hj_instance;
+
+typedef struct hj_batch_plan_s *hj_batch;
+
+/* hj_batch_plan -- prepare a batched solve of n_inst independent problems
+ * of uneven dimension, horizon, step count and point count (the method of
+ * hj_solve applied to each).  Instances are grouped by lane shape (from n)
+ * and speed profile; each group runs as ONE persistent launch whose resident
+ * lane groups take (instance, point, guess) tasks from a queue, longest
+ * instances first, and a finished group takes the next task.  The whole
+ * sequence (queue resets, the descent launches, the selection) is captured
+ * into a hipGraph that hj_batch_run replays; device pointers are fixed at
+ * planning, their contents may change between runs.  opts supplies the
+ * shared options (formula, quadrature, dtype, iterations, tolerances; mode
+ * must be HJ_GD_ADJ).  The plan owns its device scratch.  Errors as in
+ * hj_solve; *out is set on success. */
+int32_t hj_batch_plan(int32_t H_kind, int32_t J_kind, const hj_instance *inst, int32_t n_inst,
+                      const hj_opts *opts, hj_batch *out);
+
+/* Enqueue the planned solve on `stream` (a hipStream_t, NULL = null stream). */
+int32_t hj_batch_run(hj_batch plan, void *stream);
+
+/* Tasks, lane groups launched, and launches (lane-shape groups) of a plan. */
+int32_t hj_batch_info(hj_batch plan, int64_t *tasks, int64_t *groups, int32_t *launches);
+
+/* Release a plan (waits for its work to finish). */
+int32_t hj_batch_free(hj_batch plan);
 
 /* Scratch bytes hj_solve / hj_eval need for B points of G slots. */
 size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps,

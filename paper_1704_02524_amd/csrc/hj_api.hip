@@ -64,12 +64,13 @@ bool pick_shape(int n, int lpt, Shape& s) {
 
 // Layout of the scratch memory of one call.
 struct WsLayout {
-  size_t params = 0, slots = 0, ck = 0, seg = 0, total = 0;
+  size_t params = 0, slots = 0, queue = 0, ck = 0, seg = 0, total = 0;
   size_t stride = 0;  // lanes of the SoA checkpoint arrays
 };
 
+// lanes: lanes that hold adjoint checkpoints (0: one lane group per task)
 WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
-                bool grad, bool solve) {
+                bool grad, bool solve, size_t lanes = 0) {
   WsLayout L;
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
   const size_t BG = (size_t)B * (size_t)G;
@@ -79,10 +80,12 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
   if (solve) {
     L.slots = off;
     off += align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * (size_t)n * tsz, 256);
+    L.queue = off;
+    off += 256;
   }
   const bool need_adj = grad || (solve && mode == HJ_GD_ADJ);
   if (need_adj) {
-    const size_t lanes = align_up(BG * (size_t)s.lpt, 256);
+    if (lanes == 0) lanes = align_up(BG * (size_t)s.lpt, 256);
     const int Kc = std::max(1, std::min(K, nsteps));
     const size_t nck = (size_t)((nsteps + Kc - 1) / Kc) + 1;
     L.stride = lanes;
@@ -217,15 +220,38 @@ int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, ch
 // Launchers by shape and speed profile.
 template <typename T>
 hipError_t dispatch_solve(const Shape& s, int mk, const hj::SolveArgs<T>& A, int mode,
-                          hipStream_t st) {
-#define HJ_CASE(NPL, LPT)                                                               \
-  if (s.npl == NPL && s.lpt == LPT)                                                     \
-    return mk == HJ_M_TANH                                                              \
-               ? hj::launch_solve<hj::Cfg<T, NPL, LPT, HJ_M_TANH>>(A, mode, st)         \
-               : hj::launch_solve<hj::Cfg<T, NPL, LPT, HJ_M_RAT>>(A, mode, st);
+                          int64_t grid_groups, hipStream_t st) {
+#define HJ_CASE(NPL, LPT)                                                                   \
+  if (s.npl == NPL && s.lpt == LPT)                                                         \
+    return mk == HJ_M_TANH                                                                  \
+               ? hj::launch_solve<hj::Cfg<T, NPL, LPT, HJ_M_TANH>>(A, mode, grid_groups, st) \
+               : hj::launch_solve<hj::Cfg<T, NPL, LPT, HJ_M_RAT>>(A, mode, grid_groups, st);
   HJ_FOR_EACH_SHAPE(HJ_CASE)
 #undef HJ_CASE
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+int64_t dispatch_resident(const Shape& s, int mk, int mode) {
+#define HJ_CASE(NPL, LPT)                                                 \
+  if (s.npl == NPL && s.lpt == LPT)                                       \
+    return mk == HJ_M_TANH                                                \
+               ? hj::resident_groups<hj::Cfg<T, NPL, LPT, HJ_M_TANH>>(mode) \
+               : hj::resident_groups<hj::Cfg<T, NPL, LPT, HJ_M_RAT>>(mode);
+  HJ_FOR_EACH_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return 0;
+}
+
+// Lane groups of a persistent launch (0: one group per task).
+template <typename T>
+int64_t schedule_groups(const Shape& s, int mk, int mode, int sched, int64_t ntask) {
+  if (sched == HJ_SCHED_STATIC) return 0;
+  const int64_t res = dispatch_resident<T>(s, mk, mode);
+  if (res <= 0) return 0;
+  if (sched == HJ_SCHED_PERSISTENT) return std::min(res, ntask);
+  // automatic: persistent once the tasks fill the device twice over
+  return ntask > 2 * res ? res : 0;
 }
 
 template <typename T>
@@ -249,7 +275,11 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
                                      " lanes per task for n = " + std::to_string(n));
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
-  WsLayout WL = layout(s, n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true);
+  const int64_t ntask = B * (int64_t)gs->G;
+  const int64_t groups = schedule_groups<T>(s, kernel_mk(H), o->mode, o->schedule, ntask);
+  // a persistent launch holds checkpoints for its resident lanes only
+  const size_t ck_lanes = groups > 0 ? align_up((size_t)groups * s.lpt, 256) : 0;
+  WsLayout WL = layout(s, n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes);
   if ((size_t)B * gs->G * s.lpt > (size_t)UINT32_MAX * 128)
     return fail(HJ_EINVAL, "B * G too large for one launch");
   void* ws = nullptr;
@@ -304,9 +334,13 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   A.out.n_fwd = (diag && diag->n_fwd) ? diag->n_fwd : w_fwd;
   A.out.n_bwd = (diag && diag->n_bwd) ? diag->n_bwd : w_bwd;
   A.out.v = (diag && diag->v_final) ? static_cast<T*>(diag->v_final) : w_v;
+  A.ntask = ntask;
+  A.queue = groups > 0 ? reinterpret_cast<unsigned long long*>(base + WL.queue) : nullptr;
+  A.inst = nullptr;
+  A.n_inst = 0;
 
   if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
-  HJ_HIP(dispatch_solve<T>(s, kernel_mk(H), A, o->mode, st));
+  HJ_HIP(dispatch_solve<T>(s, kernel_mk(H), A, o->mode, groups, st));
   if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
   HJ_HIP(hj::launch_select<T>(B, gs->G, n, o->formula, A.out.phi, A.out.cert, A.out.v, out_u,
                               static_cast<T*>(out_argopt), out_cert, st));
@@ -387,6 +421,219 @@ int check_opts(const hj_opts* o) {
     return fail(HJ_EINVAL, "armijo_c must be in [0, 1)");
   if (o->mode == HJ_CD_FD && !(o->fd_sigma > 0.0)) return fail(HJ_EINVAL, "fd_sigma must be > 0");
   if (o->lanes_per_task < 0) return fail(HJ_EINVAL, "lanes_per_task must be >= 0");
+  if (o->schedule < HJ_SCHED_AUTO || o->schedule > HJ_SCHED_PERSISTENT)
+    return fail(HJ_EINVAL, "bad schedule");
+  return HJ_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batched plans
+// ---------------------------------------------------------------------------
+struct hj_batch_plan_s {
+  void* mem = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t tasks = 0, groups = 0;
+  int launches = 0;
+  ~hj_batch_plan_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (mem) (void)hipFree(mem);
+  }
+};
+
+namespace {
+
+// One launch of a plan: the instances that share a lane shape and profile.
+struct LaunchGroup {
+  Shape s;
+  int mk;
+  std::vector<int> inst;  // indices into the caller's array, longest first
+  int64_t tasks = 0, points = 0, groups = 0;
+  int max_steps = 0;
+  // byte offsets in the plan memory
+  size_t params = 0, table = 0, slots = 0, queue = 0, ck = 0, seg = 0, stride = 0;
+};
+
+template <typename T>
+int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_s* plan) {
+  const size_t tsz = sizeof(T);
+  // group by (shape, speed profile); within a group, longest instances first
+  std::vector<LaunchGroup> lg;
+  for (int i = 0; i < n_inst; ++i) {
+    Shape s{};
+    if (!pick_shape(inst[i].n, o->lanes_per_task, s))
+      return fail(HJ_EUNSUPPORTED, "no kernel shape for instance " + std::to_string(i));
+    const int mk = kernel_mk(&inst[i].H);
+    auto it = std::find_if(lg.begin(), lg.end(), [&](const LaunchGroup& g) {
+      return g.s.npl == s.npl && g.s.lpt == s.lpt && g.mk == mk;
+    });
+    if (it == lg.end()) {
+      lg.push_back(LaunchGroup{s, mk, {}});
+      it = lg.end() - 1;
+    }
+    it->inst.push_back(i);
+  }
+  for (LaunchGroup& g : lg) {
+    std::stable_sort(g.inst.begin(), g.inst.end(), [&](int a, int b) {
+      return (double)inst[a].nsteps * inst[a].n > (double)inst[b].nsteps * inst[b].n;
+    });
+    for (int i : g.inst) {
+      g.tasks += inst[i].B * (int64_t)inst[i].guesses.G;
+      g.points += inst[i].B;
+      g.max_steps = std::max(g.max_steps, inst[i].nsteps);
+    }
+    const int64_t res = dispatch_resident<T>(g.s, g.mk, HJ_GD_ADJ);
+    g.groups = std::max<int64_t>(1, std::min(res > 0 ? res : g.tasks, g.tasks));
+  }
+  // memory layout
+  const int Kmax = std::max(1, o->ckpt_K);
+  size_t off = 0;
+  for (LaunchGroup& g : lg) {
+    const int npad = g.s.npad();
+    const int n = inst[g.inst[0]].n;  // the rows of every instance use its own n
+    int nmax = 0;
+    for (int i : g.inst) nmax = std::max(nmax, inst[i].n);
+    g.params = off;
+    off += align_up(g.inst.size() * (size_t)npad * 3 * (tsz + 8), 256);
+    g.table = off;
+    off += align_up(g.inst.size() * sizeof(hj::InstDesc<T>), 256);
+    g.slots = off;
+    off += align_up((size_t)g.tasks * (8 + 8 + 4 * 4 + 8 + 8), 256) +
+           align_up((size_t)g.tasks * nmax * tsz, 256);
+    g.queue = off;
+    off += 256;
+    const int K = std::max(1, std::min(Kmax, g.max_steps));
+    g.stride = align_up((size_t)g.groups * g.s.lpt, 256);
+    const size_t nck = (size_t)((g.max_steps + K - 1) / K) + 1;
+    g.ck = off;
+    off += align_up(nck * 2 * g.s.npl * g.stride * tsz, 256);
+    g.seg = off;
+    off += align_up((size_t)K * 2 * g.s.npl * g.stride * tsz, 256);
+    (void)n;
+  }
+  if (hipMalloc(&plan->mem, std::max<size_t>(off, 256)) != hipSuccess) {
+    plan->mem = nullptr;
+    return fail(HJ_ENOMEM, "hipMalloc of " + std::to_string(off) + " bytes for the plan failed");
+  }
+  char* base = static_cast<char*>(plan->mem);
+  // stage parameters and instance tables
+  std::vector<hj::SolveArgs<T>> args;
+  for (LaunchGroup& g : lg) {
+    const int npad = g.s.npad();
+    std::vector<char> pbuf(g.inst.size() * (size_t)npad * 3 * (tsz + 8));
+    std::vector<hj::InstDesc<T>> table(g.inst.size());
+    int64_t task0 = 0, point0 = 0;
+    int nmax = 0;
+    for (size_t j = 0; j < g.inst.size(); ++j) {
+      const hj_instance& I = inst[g.inst[j]];
+      nmax = std::max(nmax, I.n);
+      char* q = pbuf.data() + j * (size_t)npad * 3 * (tsz + 8);
+      HostParams<T> pt = host_params<T>(&I.H, &I.J, I.n, npad);
+      HostParams<double> pd = host_params<double>(&I.H, &I.J, I.n, npad);
+      std::memcpy(q, pt.d.data(), npad * tsz);
+      std::memcpy(q + npad * tsz, pt.a2.data(), npad * tsz);
+      std::memcpy(q + 2 * npad * tsz, pt.ia2.data(), npad * tsz);
+      std::memcpy(q + 3 * npad * tsz, pd.d.data(), npad * 8);
+      std::memcpy(q + 3 * npad * tsz + npad * 8, pd.a2.data(), npad * 8);
+      std::memcpy(q + 3 * npad * tsz + 2 * npad * 8, pd.ia2.data(), npad * 8);
+      char* dq = base + g.params + j * (size_t)npad * 3 * (tsz + 8);
+      hj::InstDesc<T>& D = table[j];
+      D.P = make_problem<T>(&I.H, &I.J, I.n, I.t, I.nsteps, o->formula, o->quad,
+                            reinterpret_cast<const T*>(dq), npad);
+      D.P64 = make_problem<double>(&I.H, &I.J, I.n, I.t, I.nsteps, o->formula, o->quad,
+                                   reinterpret_cast<const double*>(dq + 3 * npad * tsz), npad);
+      D.x = static_cast<const T*>(I.x);
+      D.guesses = static_cast<const T*>(I.guesses.init);
+      D.B = I.B;
+      D.G = I.guesses.G;
+      D.R = I.guesses.R_max;
+      D.task0 = task0;
+      D.point0 = point0;
+      D.out_u = I.out_u;
+      D.out_arg = static_cast<T*>(I.out_argopt);
+      D.out_cert = I.out_cert;
+      D.diag.phi = I.diag.phi;
+      D.diag.rho = I.diag.rho;
+      D.diag.status = I.diag.status;
+      D.diag.cert = I.diag.cert;
+      D.diag.iters = I.diag.iters;
+      D.diag.attempts = I.diag.attempts;
+      D.diag.n_fwd = I.diag.n_fwd;
+      D.diag.n_bwd = I.diag.n_bwd;
+      D.diag.v = static_cast<T*>(I.diag.v_final);
+      task0 += I.B * (int64_t)I.guesses.G;
+      point0 += I.B;
+    }
+    HJ_HIP(hipMemcpy(base + g.params, pbuf.data(), pbuf.size(), hipMemcpyHostToDevice));
+    HJ_HIP(hipMemcpy(base + g.table, table.data(), table.size() * sizeof(hj::InstDesc<T>),
+                     hipMemcpyHostToDevice));
+    hj::SolveArgs<T> A;
+    std::memset(&A, 0, sizeof(A));
+    A.P = table[0].P;  // unused by the batched kernel except for n
+    A.P.n = nmax;
+    A.max_iter = o->max_iter;
+    A.K = std::max(1, std::min(Kmax, g.max_steps));
+    A.cert_fp64 = o->cert_fp64;
+    A.alpha0 = (T)o->alpha0;
+    A.sigma = (T)o->fd_sigma;
+    A.eps_step = (T)o->eps_step;
+    A.acc_rel = (T)o->acc_rel;
+    A.armijo_c = (T)o->armijo_c;
+    A.v_max = (T)o->v_max;
+    A.cert_tol = o->cert_tol;
+    A.stride = g.stride;
+    A.ck = reinterpret_cast<T*>(base + g.ck);
+    A.seg = reinterpret_cast<T*>(base + g.seg);
+    char* sp = base + g.slots;
+    const size_t BG = (size_t)g.tasks;
+    A.out.phi = reinterpret_cast<double*>(sp);
+    A.out.rho = A.out.phi + BG;
+    A.out.status = reinterpret_cast<int32_t*>(A.out.rho + BG);
+    A.out.cert = A.out.status + BG;
+    A.out.iters = A.out.cert + BG;
+    A.out.attempts = A.out.iters + BG;
+    A.out.n_fwd = reinterpret_cast<int64_t*>(A.out.attempts + BG);
+    A.out.n_bwd = A.out.n_fwd + BG;
+    A.out.v = reinterpret_cast<T*>(sp + align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256));
+    A.ntask = g.tasks;
+    A.queue = reinterpret_cast<unsigned long long*>(base + g.queue);
+    A.inst = reinterpret_cast<const hj::InstDesc<T>*>(base + g.table);
+    A.n_inst = (int)g.inst.size();
+    args.push_back(A);
+  }
+  // capture the launch sequence into a graph
+  HJ_HIP(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking));
+  HJ_HIP(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (size_t gi = 0; gi < lg.size() && err == hipSuccess; ++gi) {
+    const LaunchGroup& g = lg[gi];
+    const hj::SolveArgs<T>& A = args[gi];
+    err = dispatch_solve<T>(g.s, g.mk, A, HJ_GD_ADJ, g.groups, plan->cap);
+    if (err == hipSuccess)
+      err = hj::launch_select_batched<T>(A.inst, A.n_inst, g.points, A.P.n, o->formula,
+                                         A.out.phi, A.out.cert, A.out.v, plan->cap);
+    if (err == hipSuccess)
+      err = hj::launch_scatter_diag<T>(A.inst, A.n_inst, g.tasks, A.P.n, A.out, plan->cap);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(plan->cap, &graph);
+  if (err != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(HJ_EDEVICE, std::string("launch during capture: ") + hipGetErrorString(err));
+  }
+  HJ_HIP(e2);
+  plan->graph = graph;
+  HJ_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+  plan->launches = (int)lg.size();
+  for (const LaunchGroup& g : lg) {
+    plan->tasks += g.tasks;
+    plan->groups += g.groups;
+  }
   return HJ_OK;
 }
 
@@ -448,6 +695,59 @@ size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const 
   WsLayout a = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, false, true);
   WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
   return std::max(a.total, b.total);
+}
+
+int32_t hj_batch_plan(int32_t H_kind, int32_t J_kind, const hj_instance* inst, int32_t n_inst,
+                      const hj_opts* opts, hj_batch* out) {
+  g_last_error.clear();
+  if (!out) return fail(HJ_EINVAL, "out is required");
+  *out = nullptr;
+  if (!inst || n_inst < 1) return fail(HJ_EINVAL, "at least one instance is required");
+  hj_opts o = opts ? *opts : default_opts();
+  int rc = check_opts(&o);
+  if (rc) return rc;
+  if (o.mode != HJ_GD_ADJ) return fail(HJ_EUNSUPPORTED, "batched solves use HJ_GD_ADJ");
+  for (int i = 0; i < n_inst; ++i) {
+    const hj_instance& I = inst[i];
+    rc = check_problem(H_kind, &I.H, J_kind, &I.J, I.n, I.t, I.nsteps);
+    if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_last_error);
+    if (I.B < 1) return fail(HJ_EINVAL, "instance " + std::to_string(i) + ": B must be >= 1");
+    if (I.guesses.G < 1 || I.guesses.G > HJ_MAX_G || I.guesses.R_max < 0)
+      return fail(HJ_EINVAL, "instance " + std::to_string(i) + ": bad G or R_max");
+    if (!I.x || !I.guesses.init || !I.out_u || !I.out_argopt || !I.out_cert)
+      return fail(HJ_EINVAL, "instance " + std::to_string(i) + ": missing arrays");
+  }
+  hj_batch_plan_s* plan = new hj_batch_plan_s();
+  rc = o.dtype == HJ_F64 ? plan_t<double>(inst, n_inst, &o, plan)
+                         : plan_t<float>(inst, n_inst, &o, plan);
+  if (rc) {
+    delete plan;
+    return rc;
+  }
+  *out = plan;
+  return HJ_OK;
+}
+
+int32_t hj_batch_run(hj_batch plan, void* stream) {
+  g_last_error.clear();
+  if (!plan || !plan->exec) return fail(HJ_EINVAL, "invalid plan");
+  HJ_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+  return HJ_OK;
+}
+
+int32_t hj_batch_info(hj_batch plan, int64_t* tasks, int64_t* groups, int32_t* launches) {
+  if (!plan) return fail(HJ_EINVAL, "invalid plan");
+  if (tasks) *tasks = plan->tasks;
+  if (groups) *groups = plan->groups;
+  if (launches) *launches = plan->launches;
+  return HJ_OK;
+}
+
+int32_t hj_batch_free(hj_batch plan) {
+  if (!plan) return HJ_OK;
+  HJ_HIP(hipDeviceSynchronize());
+  delete plan;
+  return HJ_OK;
 }
 
 const char* hj_last_error(void) { return g_last_error.c_str(); }

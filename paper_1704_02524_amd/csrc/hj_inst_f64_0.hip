@@ -10,3 +10,9 @@ HJ_INSTANTIATE_BOTH(double, 2, 4)
 template hipError_t hj::launch_select<double>(int64_t, int, int, int, const double*, const int32_t*,
                                               const double*, double*, double*, int32_t*,
                                               hipStream_t);
+
+template hipError_t hj::launch_select_batched<double>(const hj::InstDesc<double>*, int, int64_t, int, int,
+                                                     const double*, const int32_t*, const double*,
+                                                     hipStream_t);
+template hipError_t hj::launch_scatter_diag<double>(const hj::InstDesc<double>*, int, int64_t, int,
+                                                   hj::SlotOut<double>, hipStream_t);

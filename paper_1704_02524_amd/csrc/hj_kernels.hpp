@@ -1,9 +1,12 @@
 // hj_kernels.hpp -- the solver kernels: objective evaluation (with optional
 // exact gradient), central-difference coordinate descent, adjoint gradient
-// descent, and per-point selection over the guess slots.  Each kernel is a
-// template over a Cfg (arithmetic type, components per lane, lanes per task,
-// speed profile); hj_inst_*.hip instantiate them and hj_api.hip dispatches.
+// descent (single problem or a batch of instances), and per-point selection
+// over the guess slots.  Each kernel is a template over a Cfg (arithmetic
+// type, components per lane, lanes per task, speed profile); hj_inst_*.hip
+// instantiate them and hj_api.hip dispatches.
 #pragma once
+
+#include <algorithm>
 
 #include "hj_device.hpp"
 #include "hj_launch.hpp"
@@ -68,34 +71,113 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C::T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// task context: the problem, query point and guesses of the task a lane
+// group is working on.  Single problem: the problem lives in the kernel
+// arguments (wave-uniform, scalar registers).  Batched: it is loaded from the
+// instance table whenever the group takes a task (per lane).
+// ---------------------------------------------------------------------------
+template <class C, bool MULTI> struct TaskCtx {
+  using T = typename C::T;
+  Problem<T> Pl;
+  Problem<double> P64l;
+  LaneParams<C> L;
+  T x[C::NPL];
+  const T* g0;  // guesses of the task: [R+1, n]
+  int R;
+
+  __device__ __forceinline__ const Problem<T>& P(const SolveArgs<T>& A) const {
+    if constexpr (MULTI) return Pl;
+    else return A.P;
+  }
+  __device__ __forceinline__ const Problem<double>& P64(const SolveArgs<T>& A) const {
+    if constexpr (MULTI) return P64l;
+    else return A.P64;
+  }
+  __device__ __forceinline__ void bind(const SolveArgs<T>& A, int64_t task, int sub) {
+    const T* xb;
+    if constexpr (MULTI) {
+      int lo = 0, hi = A.n_inst - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.inst[mid].task0 <= task)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const InstDesc<T>& I = A.inst[lo];
+      Pl = I.P;
+      P64l = I.P64;
+      L.load(Pl, sub);
+      const int n = Pl.n;
+      const int64_t lt = task - I.task0;
+      R = I.R;
+      xb = I.x + (lt / I.G) * n;
+      g0 = I.guesses + lt * (int64_t)(I.R + 1) * n;
+    } else {
+      const int n = A.P.n;
+      R = A.R;
+      xb = A.x + (task / A.G) * n;
+      g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
+    }
+    load_row<T, C::NPL>(xb, P(A).n, sub, x);
+  }
+};
+
+// Next task for a lane group: the group's leader takes an index from the
+// queue and the group shares it.
+template <int LPT>
+__device__ __forceinline__ int64_t pop_task(unsigned long long* queue, int sub) {
+  unsigned long long t = 0;
+  if (sub == 0) t = atomicAdd(queue, 1ULL);
+  if (LPT > 1) {
+    const int leader = (int)(threadIdx.x % 64) - sub;
+    const int lo = __shfl((int)(t & 0xffffffffULL), leader, 64);
+    const int hi = __shfl((int)(t >> 32), leader, 64);
+    t = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+  }
+  return (int64_t)t;
+}
+
+// ---------------------------------------------------------------------------
 // shared per-slot bookkeeping
 // ---------------------------------------------------------------------------
 struct SlotBest {
-  double phi = __builtin_nan(""), rho = __builtin_nan("");
-  int32_t cert = -1, status = HJ_ST_DIVERGED, iters = 0, attempts = 0;
-  int64_t n_fwd = 0, n_bwd = 0;
+  double phi, rho;
+  int32_t cert, status, iters, attempts;
+  int64_t n_fwd, n_bwd;
+  __device__ __forceinline__ void reset() {
+    phi = __builtin_nan("");
+    rho = __builtin_nan("");
+    cert = -1;
+    status = HJ_ST_DIVERGED;
+    iters = 0;
+    attempts = 0;
+    n_fwd = 0;
+    n_bwd = 0;
+  }
 };
 
 // Certificate and objective of a finished run, in FP64.  FP32 runs with the
 // FP64 certificate re-solve the characteristic in FP64 at the final v.
-template <class C>
-__device__ __forceinline__ void final_values(const SolveArgs<typename C::T>& A, int sub,
-                                             const typename C::T (&x)[C::NPL],
+template <class C, bool MULTI>
+__device__ __forceinline__ void final_values(const SolveArgs<typename C::T>& A,
+                                             const TaskCtx<C, MULTI>& tc, int sub,
                                              const typename C::T (&v)[C::NPL],
                                              typename C::T phi, typename C::T rho,
                                              double& phi64, double& rho64) {
   if constexpr (sizeof(typename C::T) == 4) {
     if (A.cert_fp64) {
       using C64 = Cfg<double, C::NPL, C::LPT, C::MK>;
+      const Problem<double>& P64 = tc.P64(A);
       LaneParams<C64> L64;
-      L64.load(A.P64, sub);
+      L64.load(P64, sub);
       double x64[C::NPL], v64[1][C::NPL], ph[1], rh[1];
 #pragma unroll
       for (int k = 0; k < C::NPL; ++k) {
-        x64[k] = (double)x[k];
+        x64[k] = (double)tc.x[k];
         v64[0][k] = (double)v[k];
       }
-      forward<C64, 1, false>(A.P64, L64, x64, v64, ph, rh);
+      forward<C64, 1, false>(P64, L64, x64, v64, ph, rh);
       phi64 = ph[0];
       rho64 = rh[0];
       return;
@@ -106,9 +188,9 @@ __device__ __forceinline__ void final_values(const SolveArgs<typename C::T>& A, 
 }
 
 // Record the end of one attempt; returns true when the slot is finished.
-template <class C>
-__device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A, int sub,
-                                            int64_t task, const typename C::T (&x)[C::NPL],
+template <class C, bool MULTI>
+__device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A,
+                                            const TaskCtx<C, MULTI>& tc, int sub, int64_t task,
                                             const typename C::T (&v)[C::NPL], typename C::T phi,
                                             typename C::T rho, int status, int it, int att,
                                             SlotBest& best) {
@@ -117,7 +199,7 @@ __device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A, i
     phi64 = (double)phi;
     rho64 = __builtin_nan("");
   } else {
-    final_values<C>(A, sub, x, v, phi, rho, phi64, rho64);
+    final_values<C, MULTI>(A, tc, sub, v, phi, rho, phi64, rho64);
   }
   best.iters += it;
   best.attempts = att + 1;
@@ -128,20 +210,24 @@ __device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A, i
     best.rho = rho64;
     best.cert = certified ? 1 : 0;
     best.status = status;
-    store_row<typename C::T, C::NPL>(A.out.v + task * A.P.n, A.P.n, sub, v);
+    const int n = tc.P(A).n;
+    // slot records use the row stride A.P.n (the largest n of a batch)
+    store_row<typename C::T, C::NPL>(A.out.v + task * A.P.n, n, sub, v);
   }
-  return certified || (att + 1 > A.R);
+  return certified || (att + 1 > tc.R);
 }
 
-template <class C>
-__device__ __forceinline__ void write_slot(const SolveArgs<typename C::T>& A, int sub,
-                                           int64_t task, const SlotBest& best) {
+template <class C, bool MULTI>
+__device__ __forceinline__ void write_slot(const SolveArgs<typename C::T>& A,
+                                           const TaskCtx<C, MULTI>& tc, int sub, int64_t task,
+                                           const SlotBest& best) {
   using T = typename C::T;
+  const int n = tc.P(A).n;
   if (best.cert < 0) {
     T nanv[C::NPL];
 #pragma unroll
     for (int k = 0; k < C::NPL; ++k) nanv[k] = T(__builtin_nan(""));
-    store_row<T, C::NPL>(A.out.v + task * A.P.n, A.P.n, sub, nanv);
+    store_row<T, C::NPL>(A.out.v + task * A.P.n, n, sub, nanv);
   }
   if (sub != 0) return;
   if (A.out.phi) A.out.phi[task] = best.phi;
@@ -181,6 +267,14 @@ __device__ __forceinline__ int stop_status(const SolveArgs<typename C::T>& A,
   return -1;
 }
 
+// After a slot: the next task of the group, or -1 when there is none.
+template <class C>
+__device__ __forceinline__ int64_t next_task(const SolveArgs<typename C::T>& A, int sub) {
+  if (!A.queue) return -1;
+  const int64_t t = pop_task<C::LPT>(A.queue, sub);
+  return t < A.ntask ? t : -1;
+}
+
 // ---------------------------------------------------------------------------
 // cyclic coordinate descent with central differences (Algorithm 1; one
 // iteration = one sweep over the n coordinates; the step halves when a trial
@@ -192,17 +286,16 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
   constexpr int NPL = C::NPL, LPT = C::LPT;
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = threadIdx.x % LPT;
-  const int64_t task = (int64_t)(lane / LPT);
-  if (task >= A.B * A.G) return;
-  const int64_t b = task / A.G;
+  int64_t task = (int64_t)(lane / LPT);
+  if (task >= A.ntask) return;
+  TaskCtx<C, false> tc;
+  tc.L.load(A.P, sub);
+  tc.bind(A, task, sub);
   const int n = A.P.n;
-  LaneParams<C> L;
-  L.load(A.P, sub);
-  T x[NPL], v[NPL];
-  load_row<T, NPL>(A.x + b * n, n, sub, x);
-  const T* g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
-  load_row<T, NPL>(g0, n, sub, v);
+  T v[NPL];
+  load_row<T, NPL>(tc.g0, n, sub, v);
   SlotBest best;
+  best.reset();
   int att = 0, it = 0, j = 0;
   bool start = true;
   T alpha = A.alpha0, phi = T(0), rho = T(0), smax = T(0);
@@ -215,7 +308,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
       va[0][k] = on ? v[k] + A.sigma : v[k];
       va[1][k] = on ? v[k] - A.sigma : v[k];
     }
-    forward<C, 2, false>(A.P, L, x, va, fp, rp);
+    forward<C, 2, false>(A.P, tc.L, tc.x, va, fp, rp);
     int status = -1;
     if (start) {
       best.n_fwd += 1;
@@ -237,7 +330,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
       T vt[1][NPL], ft[1], rt[1];
 #pragma unroll
       for (int k = 0; k < NPL; ++k) vt[0][k] = (sub * NPL + k == j) ? v[k] - step : v[k];
-      forward<C, 1, false>(A.P, L, x, vt, ft, rt);
+      forward<C, 1, false>(A.P, tc.L, tc.x, vt, ft, rt);
       best.n_fwd += 3;
       if (accept_step(A, ft[0], phi, alpha * gj * gj)) {
 #pragma unroll
@@ -255,58 +348,63 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
       }
     }
     if (status >= 0) {
-      if (end_attempt<C>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
-      ++att;
-      load_row<T, NPL>(g0 + (int64_t)att * n, n, sub, v);
+      if (end_attempt<C, false>(A, tc, sub, task, v, phi, rho, status, it, att, best)) {
+        write_slot<C, false>(A, tc, sub, task, best);
+        task = next_task<C>(A, sub);
+        if (task < 0) break;
+        tc.bind(A, task, sub);
+        best.reset();
+        att = 0;
+      } else {
+        ++att;
+      }
+      load_row<T, NPL>(tc.g0 + (int64_t)att * n, n, sub, v);
       start = true;
     }
   }
-  write_slot<C>(A, sub, task, best);
 }
 
 // ---------------------------------------------------------------------------
 // gradient descent with the exact discrete gradient (adjoint + checkpoints)
 // ---------------------------------------------------------------------------
-template <class C>
+template <class C, bool MULTI>
 __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
   constexpr int NPL = C::NPL, LPT = C::LPT;
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = threadIdx.x % LPT;
-  const int64_t task = (int64_t)(lane / LPT);
-  if (task >= A.B * A.G) return;
-  const int64_t b = task / A.G;
-  const int n = A.P.n;
-  LaneParams<C> L;
-  L.load(A.P, sub);
-  T x[NPL], v[NPL], g[NPL];
-  load_row<T, NPL>(A.x + b * n, n, sub, x);
-  const T* g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
-  load_row<T, NPL>(g0, n, sub, v);
+  int64_t task = (int64_t)(lane / LPT);
+  if (task >= A.ntask) return;
+  TaskCtx<C, MULTI> tc;
+  if constexpr (!MULTI) tc.L.load(A.P, sub);
+  tc.bind(A, task, sub);
+  T v[NPL], g[NPL];
+  load_row<T, NPL>(tc.g0, tc.P(A).n, sub, v);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) g[k] = T(0);
   SlotBest best;
+  best.reset();
   int att = 0, it = 0;
   bool start = true;
   T alpha = A.alpha0, phi = T(0), rho = T(0);
   while (true) {
+    const Problem<T>& P = tc.P(A);
     // trial point
     T vt[1][NPL], ft[1], rt[1], smax = T(0), gg = T(0);
     if (start) {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) vt[0][k] = v[k];
     } else {
-      T gm = T(0), g2[NPL];
+      T gm = T(0);
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         gm = nanmax(gm, dabs(g[k]));
-        g2[k] = g[k] * g[k];
         vt[0][k] = v[k] - alpha * g[k];
       }
       smax = alpha * gmax<LPT>(gm);
-      gg = gsum<LPT>(tree_sum<NPL>(g2));
+      gg = gsum<LPT>(dot2<NPL>(g, g));
     }
-    forward<C, 1, true>(A.P, L, x, vt, ft, rt, A.ck, A.stride, lane, A.K);
+    forward<C, 1, true>(P, tc.L, tc.x, vt, ft, rt, A.ck, A.stride, lane, A.K);
     best.n_fwd += 1;
     const bool acc = start || accept_step(A, ft[0], phi, alpha * gg);
     if (acc) {
@@ -319,7 +417,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
     }
     if (acc && isfinite(phi)) {
       T gx[NPL];
-      backward<C>(A.P, L, x, v, A.ck, A.seg, A.stride, lane, A.K, g, gx);
+      backward<C>(P, tc.L, tc.x, v, A.ck, A.seg, A.stride, lane, A.K, g, gx);
       best.n_bwd += 1;
     }
     int status = -1;
@@ -336,13 +434,20 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
       status = stop_status<C>(A, v, phi, smax, alpha, it);
     }
     if (status >= 0) {
-      if (end_attempt<C>(A, sub, task, x, v, phi, rho, status, it, att, best)) break;
-      ++att;
-      load_row<T, NPL>(g0 + (int64_t)att * n, n, sub, v);
+      if (end_attempt<C, MULTI>(A, tc, sub, task, v, phi, rho, status, it, att, best)) {
+        write_slot<C, MULTI>(A, tc, sub, task, best);
+        task = next_task<C>(A, sub);
+        if (task < 0) break;
+        tc.bind(A, task, sub);
+        best.reset();
+        att = 0;
+      } else {
+        ++att;
+      }
+      load_row<T, NPL>(tc.g0 + (int64_t)att * tc.P(A).n, tc.P(A).n, sub, v);
       start = true;
     }
   }
-  write_slot<C>(A, sub, task, best);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,18 +455,17 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
 // objective, ties to the lowest slot)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_select(int64_t B, int G, int n, int formula,
-                                                const double* s_phi, const int32_t* s_cert,
-                                                const T* s_v, double* out_u, T* out_arg,
-                                                int32_t* out_cert) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= B) return;
+__device__ __forceinline__ void select_point(int64_t b, int64_t task0, int G, int n,
+                                             int vstride, int formula,
+                                             const double* s_phi, const int32_t* s_cert,
+                                             const T* s_v, double* out_u, T* out_arg,
+                                             int32_t* out_cert) {
   int pick = -1, pc = -1;
   double best = 0.0;
   for (int g = 0; g < G; ++g) {
-    const int c = s_cert[b * G + g];
+    const int c = s_cert[task0 + g];
     if (c < 0) continue;
-    const double ph = s_phi[b * G + g];
+    const double ph = s_phi[task0 + g];
     if (c > pc || (c == pc && ph < best)) {
       pick = g;
       pc = c;
@@ -374,22 +478,107 @@ __global__ __launch_bounds__(256) void k_select(int64_t B, int G, int n, int for
     for (int i = 0; i < n; ++i) out_arg[b * n + i] = T(__builtin_nan(""));
   } else {
     out_u[b] = (formula == HJ_LAX) ? best : -best;
-    for (int i = 0; i < n; ++i) out_arg[b * n + i] = s_v[(b * G + pick) * n + i];
+    for (int i = 0; i < n; ++i) out_arg[b * n + i] = s_v[(task0 + pick) * vstride + i];
   }
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_select(int64_t B, int G, int n, int formula,
+                                                const double* s_phi, const int32_t* s_cert,
+                                                const T* s_v, double* out_u, T* out_arg,
+                                                int32_t* out_cert) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  select_point<T>(b, b * G, G, n, n, formula, s_phi, s_cert, s_v, out_u, out_arg, out_cert);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_select_batched(const InstDesc<T>* inst, int n_inst,
+                                                        int64_t total, int n, int formula,
+                                                        const double* s_phi,
+                                                        const int32_t* s_cert, const T* s_v) {
+  const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gp >= total) return;
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].point0 <= gp)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const InstDesc<T>& I = inst[lo];
+  const int64_t b = gp - I.point0;
+  select_point<T>(b, I.task0 + b * I.G, I.G, I.P.n, n, formula, s_phi, s_cert, s_v, I.out_u,
+                  I.out_arg, I.out_cert);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_diag(const InstDesc<T>* inst, int n_inst,
+                                                      int64_t total, int n, SlotOut<T> rec) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].task0 <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const SlotOut<T>& D = inst[lo].diag;
+  const int64_t lt = t - inst[lo].task0;
+  if (D.phi) D.phi[lt] = rec.phi[t];
+  if (D.rho) D.rho[lt] = rec.rho[t];
+  if (D.status) D.status[lt] = rec.status[t];
+  if (D.cert) D.cert[lt] = rec.cert[t];
+  if (D.iters) D.iters[lt] = rec.iters[t];
+  if (D.attempts) D.attempts[lt] = rec.attempts[t];
+  if (D.n_fwd) D.n_fwd[lt] = rec.n_fwd[t];
+  if (D.n_bwd) D.n_bwd[lt] = rec.n_bwd[t];
+  if (D.v)
+    for (int i = 0; i < inst[lo].P.n; ++i) D.v[lt * inst[lo].P.n + i] = rec.v[t * n + i];
+}
+
+static __global__ void k_queue_reset(unsigned long long* q, unsigned long long v) { *q = v; }
 
 // ---------------------------------------------------------------------------
 // launchers (explicitly instantiated in hj_inst_*.hip)
 // ---------------------------------------------------------------------------
 template <class C>
-hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, hipStream_t st) {
-  const int64_t threads = A.B * A.G * C::LPT;
+int64_t resident_groups(int mode) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e;
+  if (mode == HJ_CD_FD)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_cd<C>, 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false>, 256, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  return (int64_t)cus * per_cu * (256 / C::LPT);
+}
+
+template <class C>
+hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, int64_t grid_groups,
+                        hipStream_t st) {
   const int block = 256;
-  const int64_t grid = (threads + block - 1) / block;
+  const int64_t groups = grid_groups > 0 ? std::min<int64_t>(grid_groups, A.ntask) : A.ntask;
+  const int64_t grid = (groups * C::LPT + block - 1) / block;
+  // the queue hands out tasks after the ones every launched group starts with
+  if (A.queue) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, st, A.queue,
+                       (unsigned long long)(grid * block / C::LPT));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (mode == HJ_CD_FD)
     hipLaunchKernelGGL(k_solve_cd<C>, dim3((unsigned)grid), dim3(block), 0, st, A);
+  else if (A.inst)
+    hipLaunchKernelGGL((k_solve_gd<C, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
   else
-    hipLaunchKernelGGL(k_solve_gd<C>, dim3((unsigned)grid), dim3(block), 0, st, A);
+    hipLaunchKernelGGL((k_solve_gd<C, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
   return hipGetLastError();
 }
 
@@ -413,12 +602,34 @@ hipError_t launch_select(int64_t B, int G, int n, int formula, const double* s_p
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_select_batched(const InstDesc<T>* inst, int n_inst, int64_t total_points,
+                                 int n, int formula, const double* s_phi,
+                                 const int32_t* s_cert, const T* s_v, hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (total_points + block - 1) / block;
+  hipLaunchKernelGGL(k_select_batched<T>, dim3((unsigned)grid), dim3(block), 0, st, inst,
+                     n_inst, total_points, n, formula, s_phi, s_cert, s_v);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scatter_diag(const InstDesc<T>* inst, int n_inst, int64_t total_tasks, int n,
+                               SlotOut<T> rec, hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (total_tasks + block - 1) / block;
+  hipLaunchKernelGGL(k_scatter_diag<T>, dim3((unsigned)grid), dim3(block), 0, st, inst, n_inst,
+                     total_tasks, n, rec);
+  return hipGetLastError();
+}
+
 }  // namespace hj
 
 // Explicit instantiation of the launchers of one Cfg.
 #define HJ_INSTANTIATE(T, NPL, LPT, MK)                                                     \
   template hipError_t hj::launch_solve<hj::Cfg<T, NPL, LPT, MK>>(const hj::SolveArgs<T>&,  \
-                                                                 int, hipStream_t);         \
+                                                                 int, int64_t, hipStream_t); \
+  template int64_t hj::resident_groups<hj::Cfg<T, NPL, LPT, MK>>(int);                     \
   template hipError_t hj::launch_eval<hj::Cfg<T, NPL, LPT, MK>>(const hj::EvalArgs<T>&,    \
                                                                 hipStream_t);
 #define HJ_INSTANTIATE_BOTH(T, NPL, LPT) \

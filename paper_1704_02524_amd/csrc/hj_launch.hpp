@@ -20,6 +20,23 @@ template <typename T> struct SlotOut {
   T* v;
 };
 
+// One problem instance of a batched solve (all instances of one launch share
+// the lane shape, hence the component count per lane).
+template <typename T> struct InstDesc {
+  Problem<T> P;
+  Problem<double> P64;
+  const T* x;        // [B, n]
+  const T* guesses;  // [B, G, R+1, n]
+  int64_t B;
+  int G, R;
+  int64_t task0;     // global index of the instance's first task
+  int64_t point0;    // global index of the instance's first point
+  double* out_u;     // [B]
+  T* out_arg;        // [B, n]
+  int32_t* out_cert; // [B]
+  SlotOut<T> diag;   // optional per-slot copies [B, G] (null members)
+};
+
 template <typename T> struct SolveArgs {
   Problem<T> P;
   Problem<double> P64;  // the same problem in FP64 (certificate of FP32 runs)
@@ -34,7 +51,15 @@ template <typename T> struct SolveArgs {
   T* ck;                // adjoint checkpoints, SoA over `stride` lanes
   T* seg;               // adjoint segment scratch
   size_t stride;
-  SlotOut<T> out;
+  SlotOut<T> out;       // per-slot records, indexed by global task
+  // work distribution: ntask tasks; with `queue` set, the launch is
+  // persistent and a task group that finishes pops the next task index from
+  // *queue (which must start at the number of task groups launched)
+  int64_t ntask;
+  unsigned long long* queue;
+  // batched instances (nullptr: the single problem above)
+  const InstDesc<T>* inst;
+  int n_inst;
 };
 
 template <typename T> struct EvalArgs {
@@ -53,14 +78,32 @@ template <typename T> struct EvalArgs {
   size_t stride;
 };
 
+// Launch a descent kernel over A.ntask tasks.  grid_groups = 0: one task
+// group per task (no queue); otherwise a persistent launch of grid_groups
+// task groups fed by A.queue (reset by this call with a small kernel, so the
+// sequence can be captured in a graph).
 template <class C>
-hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, hipStream_t st);
+hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, int64_t grid_groups,
+                        hipStream_t st);
+// Task groups the device holds at once for this kernel (occupancy x CUs).
+template <class C>
+int64_t resident_groups(int mode);
 template <class C>
 hipError_t launch_eval(const EvalArgs<typename C::T>& A, hipStream_t st);
 template <typename T>
 hipError_t launch_select(int64_t B, int G, int n, int formula, const double* s_phi,
                          const int32_t* s_cert, const T* s_v, double* out_u, T* out_arg,
                          int32_t* out_cert, hipStream_t st);
+// Selection for batched instances: total_points points over n_inst
+// instances (each instance's points are [point0, point0 + B)).
+template <typename T>
+hipError_t launch_select_batched(const InstDesc<T>* inst, int n_inst, int64_t total_points,
+                                 int n, int formula, const double* s_phi,
+                                 const int32_t* s_cert, const T* s_v, hipStream_t st);
+// Copy the per-slot records of a batched launch to the instances' diag arrays.
+template <typename T>
+hipError_t launch_scatter_diag(const InstDesc<T>* inst, int n_inst, int64_t total_tasks, int n,
+                               SlotOut<T> rec, hipStream_t st);
 
 // Lane shapes compiled for both arithmetic types and both speed profiles
 // (components per lane NPL x lanes per task LPT), in order of preference

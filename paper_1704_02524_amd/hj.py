@@ -46,13 +46,23 @@ class Opts(C.Structure):
                 ("cert_tol", C.c_double), ("v_max", C.c_double), ("acc_rel", C.c_double),
                 ("armijo_c", C.c_double),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
-                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p)]
+                ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("schedule", C.c_int32),
+                ("reserved2", C.c_int32)]
+
+SCHED_AUTO, SCHED_STATIC, SCHED_PERSISTENT = 0, 1, 2
 
 
 class SlotDiag(C.Structure):
     _fields_ = [("phi", C.c_void_p), ("rho", C.c_void_p), ("status", C.c_void_p),
                 ("cert", C.c_void_p), ("iters", C.c_void_p), ("attempts", C.c_void_p),
                 ("n_fwd", C.c_void_p), ("n_bwd", C.c_void_p), ("v_final", C.c_void_p)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("n", C.c_int32), ("t", C.c_double), ("nsteps", C.c_int32), ("H", HParams),
+                ("J", JParams), ("x", C.c_void_p), ("B", C.c_int64), ("guesses", Guesses),
+                ("out_u", C.c_void_p), ("out_argopt", C.c_void_p), ("out_cert", C.c_void_p),
+                ("diag", SlotDiag)]
 
 
 class HJError(RuntimeError):
@@ -87,6 +97,16 @@ def lib():
         L.hj_last_error.argtypes = []
         L.hj_version.restype = C.c_int32
         L.hj_version.argtypes = []
+        L.hj_batch_plan.restype = C.c_int32
+        L.hj_batch_plan.argtypes = [C.c_int32, C.c_int32, C.POINTER(Instance), C.c_int32,
+                                    C.POINTER(Opts), C.POINTER(C.c_void_p)]
+        L.hj_batch_run.restype = C.c_int32
+        L.hj_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+        L.hj_batch_info.restype = C.c_int32
+        L.hj_batch_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int32)]
+        L.hj_batch_free.restype = C.c_int32
+        L.hj_batch_free.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -243,3 +263,77 @@ class HJFunctional(torch.autograd.Function):
 
 def version() -> int:
     return lib().hj_version()
+
+
+class BatchPlan:
+    """hj_batch_plan over a list of workloads (same formula, quadrature,
+    dtype and solve options; any n, t, N, B).  Owns the device inputs and
+    outputs of every instance; run() replays the captured graph."""
+
+    def __init__(self, wls, device="cuda", diag=True, **opt_over):
+        assert len(wls) > 0
+        self.wls = wls
+        self.inputs, self.outputs, self._probs = [], [], []
+        arr = (Instance * len(wls))()
+        for i, wl in enumerate(wls):
+            x, g = device_inputs(wl, device)
+            dt = _tdtype(wl.dtype)
+            B, G, n = wl.B, wl.G, wl.n
+            out = dict(u=torch.empty(B, dtype=torch.float64, device=device),
+                       argopt=torch.empty(B, n, dtype=dt, device=device),
+                       cert=torch.empty(B, dtype=torch.int32, device=device))
+            if diag:
+                out.update(
+                    slot_phi=torch.empty(B, G, dtype=torch.float64, device=device),
+                    slot_rho=torch.empty(B, G, dtype=torch.float64, device=device),
+                    slot_status=torch.empty(B, G, dtype=torch.int32, device=device),
+                    slot_cert=torch.empty(B, G, dtype=torch.int32, device=device),
+                    slot_iters=torch.empty(B, G, dtype=torch.int32, device=device),
+                    slot_attempts=torch.empty(B, G, dtype=torch.int32, device=device),
+                    slot_fwd=torch.empty(B, G, dtype=torch.int64, device=device),
+                    slot_bwd=torch.empty(B, G, dtype=torch.int64, device=device),
+                    slot_v=torch.empty(B, G, n, dtype=dt, device=device))
+            prob = Problem(wl)
+            self._probs.append(prob)
+            self.inputs.append((x, g))
+            self.outputs.append(out)
+            I = arr[i]
+            I.n, I.t, I.nsteps = n, float(wl.t), int(wl.nsteps)
+            I.H, I.J = prob.H, prob.J
+            I.x, I.B = _ptr(x), B
+            I.guesses = Guesses(G, wl.R_max, _ptr(g))
+            I.out_u, I.out_argopt, I.out_cert = _ptr(out["u"]), _ptr(out["argopt"]), \
+                _ptr(out["cert"])
+            if diag:
+                I.diag = SlotDiag(_ptr(out["slot_phi"]), _ptr(out["slot_rho"]),
+                                  _ptr(out["slot_status"]), _ptr(out["slot_cert"]),
+                                  _ptr(out["slot_iters"]), _ptr(out["slot_attempts"]),
+                                  _ptr(out["slot_fwd"]), _ptr(out["slot_bwd"]),
+                                  _ptr(out["slot_v"]))
+        self._arr = arr
+        o = make_opts(wls[0], **opt_over)
+        h = C.c_void_p()
+        _check(lib().hj_batch_plan(HJ_H_QUADRATIC, HJ_J_ELLIPSOID, arr, len(wls), C.byref(o),
+                                   C.byref(h)))
+        self.handle = h
+
+    def info(self):
+        t, g, nl = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().hj_batch_info(self.handle, C.byref(t), C.byref(g), C.byref(nl)))
+        return dict(tasks=t.value, groups=g.value, launches=nl.value)
+
+    def run(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().hj_batch_run(self.handle, C.c_void_p(s.cuda_stream)))
+        return self.outputs
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib().hj_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,102 @@
+"""Persistent (work-queue) scheduling and batched instances in one
+graph-captured launch sequence, checked against the single-problem path and
+the FP64 reference."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle, build as build_oracle
+from paper_1704_02524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+build_oracle()
+
+
+@pytest.fixture(scope="module")
+def hj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_02524_amd import hj as _hj
+    return _hj
+
+
+def _host(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+@pytest.mark.parametrize("lpt", [1, 2])
+@pytest.mark.parametrize("mode", [W.GD_ADJ, W.CD_FD])
+def test_persistent_schedule_equals_static(hj, lpt, mode):
+    """Lane groups that pop tasks from the queue compute exactly what one
+    group per task computes (results are indexed by task, not by lane)."""
+    wl = W.c1_hopf_n10(B=96, mode=mode)
+    if mode == W.CD_FD:
+        wl = wl.with_(guesses=wl.guesses[:, :4].copy(), max_iter=30)
+    x, g = hj.device_inputs(wl)
+    a = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_STATIC))
+    # a persistent launch with far fewer groups than tasks
+    b = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_PERSISTENT))
+    for k in a:
+        np.testing.assert_array_equal(np.nan_to_num(a[k]), np.nan_to_num(b[k]), err_msg=k)
+
+
+def _batch(n_inst=8, max_points=20, dtype=W.F64, G=4):
+    wls = W.c2_batched(dtype=dtype, n_inst=n_inst, max_points=max_points)
+    return [w.with_(guesses=w.guesses[:, :G].copy(), max_iter=120) for w in wls]
+
+
+def test_batched_equals_single_solves_and_graph_replays(hj):
+    wls = _batch()
+    plan = hj.BatchPlan(wls)
+    info = plan.info()
+    assert info["tasks"] == sum(w.B * w.G for w in wls)
+    assert info["launches"] == len({w.n for w in wls})
+    singles = [_host(hj.solve(w, *hj.device_inputs(w))) for w in wls]
+    for rep in range(3):
+        outs = plan.run()
+        torch.cuda.synchronize()
+        for w, out, ref in zip(wls, outs, singles):
+            got = _host(out)
+            np.testing.assert_array_equal(got["cert"], ref["cert"])
+            np.testing.assert_allclose(got["u"], ref["u"], rtol=1e-13, atol=1e-13)
+            np.testing.assert_array_equal(got["slot_fwd"], ref["slot_fwd"])
+            np.testing.assert_allclose(np.nan_to_num(got["argopt"]),
+                                       np.nan_to_num(ref["argopt"]), rtol=1e-12, atol=1e-12)
+        # eager work between replays: clobber the outputs and run other kernels
+        for out in outs:
+            for v in out.values():
+                v.zero_()
+        _ = torch.randn(1 << 20, device="cuda").sum().item()
+        torch.cuda.synchronize()
+    plan.free()
+
+
+def test_batched_matches_reference(hj):
+    wls = _batch(n_inst=6, max_points=6)
+    plan = hj.BatchPlan(wls)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for w, out in zip(wls, outs):
+        got = _host(out)
+        o = Oracle.from_workload(w)
+        ref = o.solve(w.x[:2], w.guesses[:2], Oracle.opts_from_workload(w))
+        np.testing.assert_array_equal(got["cert"][:2], ref["cert"])
+        fin = ref["cert"] >= 0
+        err = np.abs(got["u"][:2][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
+        assert err.max(initial=0.0) <= 1e-9, (w.name, err)
+    plan.free()
+
+
+def test_batched_fp32(hj):
+    wls = _batch(n_inst=4, max_points=8, dtype=W.F32)
+    plan = hj.BatchPlan(wls)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for w, out in zip(wls, outs):
+        got = _host(out)
+        ref = Oracle.from_workload(w).solve(w.x[:2], w.guesses[:2], Oracle.opts_from_workload(w))
+        fin = (ref["cert"] >= 0) & (got["cert"][:2] >= 0)
+        err = np.abs(got["u"][:2][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
+        assert err.max(initial=0.0) <= 1e-4, (w.name, err)
+    plan.free()
