@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhj.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["hj_api.hip"] + [f"hj_inst_{t}_{i}.hip" for t in ("f64", "f32") for i in range(4)]
+SOURCES = ["hj_api.hip"] + [f"hj_inst_{t}_{i}.hip" for t in ("f64", "f32") for i in range(5)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -42,9 +42,19 @@ DevScratch g_ws[64];
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// The lane shape for n: with lpt == 0 the first default shape covering n,
-// else the smallest compiled shape with that many lanes per task.
-bool pick_shape(int n, int lpt, Shape& s) {
+// The lane shape for n: with drift, the smallest matrix-core shape covering
+// n (4 lanes per task); otherwise with lpt == 0 the first default shape
+// covering n, else the smallest compiled shape with that many lanes per task.
+bool pick_shape(int n, int lpt, bool drift, Shape& s) {
+  if (drift) {
+    if (lpt != 0 && lpt != 4) return false;
+    for (int npl : hj::kDriftNpl)
+      if (n <= 4 * npl) {
+        s = Shape{npl, 4, true};
+        return true;
+      }
+    return false;
+  }
   if (lpt == 0) {
     for (int i = 0; i < hj::kNumDefaultShapes; ++i)
       if (n <= hj::kShapes[i].npad()) {
@@ -62,6 +72,34 @@ bool pick_shape(int n, int lpt, Shape& s) {
   return found;
 }
 
+// Elements of the MFMA operand table of A and A^T for NPL components per lane.
+size_t drift_table_len(int npl) { return (size_t)2 * (npl / 4) * npl * 64; }
+
+// The table itself: element [m][ib][kb][l] = M_m[16 ib + row(l % 16)][4 kb + l / 16]
+// with M_0 = A, M_1 = A^T (zero outside n x n): lane l supplies that element
+// of the 16x4 block (ib, kb) as the MFMA's first operand.  The FP64 16x16x4
+// MFMA returns block row 4 r + l / 16 in register r of lane l, the FP32 one
+// row 4 (l / 16) + r; row() reorders the FP32 rows so that in both cases
+// register r of lane `sub` receives component 16 ib + 4 r + sub, which that
+// lane owns (slot 4 ib + r).
+template <typename T>
+std::vector<T> drift_table(const double* A, int n, int npl) {
+  const int NB = npl / 4;
+  std::vector<T> t(drift_table_len(npl), T(0));
+  for (int m = 0; m < 2; ++m)
+    for (int ib = 0; ib < NB; ++ib)
+      for (int kb = 0; kb < npl; ++kb)
+        for (int l = 0; l < 64; ++l) {
+          const int i = l % 16;
+          const int ri = sizeof(T) == 8 ? i : 4 * (i % 4) + i / 4;
+          const int row = 16 * ib + ri, col = 4 * kb + l / 16;
+          double val = 0.0;
+          if (row < n && col < n) val = (m == 0) ? A[row * n + col] : A[col * n + row];
+          t[(((size_t)m * NB + ib) * npl + kb) * 64 + l] = (T)val;
+        }
+  return t;
+}
+
 // Layout of the scratch memory of one call.
 struct WsLayout {
   size_t params = 0, slots = 0, queue = 0, ck = 0, seg = 0, total = 0;
@@ -77,6 +115,7 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
   size_t off = 0;
   L.params = off;
   off += align_up((size_t)s.npad() * 3 * (8 + tsz), 256);
+  if (s.dr) off += align_up(drift_table_len(s.npl) * (8 + tsz), 256);
   if (solve) {
     L.slots = off;
     off += align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * (size_t)n * tsz, 256);
@@ -144,7 +183,9 @@ int check_problem(int H_kind, const hj_h_params* H, int J_kind, const hj_j_param
   if (H->e != 1 && H->e != 2) return fail(HJ_EINVAL, "e must be 1 or 2");
   if (H->m_kind == HJ_M_TANH && !(H->s > 0.0)) return fail(HJ_EINVAL, "tanh scale s must be > 0");
   if (!H->d || !J->a) return fail(HJ_EINVAL, "d and a arrays are required");
-  if (H->A) return fail(HJ_EUNSUPPORTED, "the drift matrix A is not supported by this build");
+  if (H->A)
+    for (int i = 0; i < n * n; ++i)
+      if (!std::isfinite(H->A[i])) return fail(HJ_EINVAL, "drift matrix entries must be finite");
   for (int i = 0; i < n; ++i)
     if (!(J->a[i] != 0.0) || !std::isfinite(J->a[i]))
       return fail(HJ_EINVAL, "ellipsoid axes must be finite and nonzero");
@@ -190,18 +231,24 @@ hj::Problem<T> make_problem(const hj_h_params* H, const hj_j_params* J, int n, d
   P.d = base;
   P.a2 = base + npad;
   P.ia2 = base + 2 * npad;
+  P.aop = nullptr;
   return P;
 }
 
-// Stage d, a^2, 1/a^2 (in T and in double) into the params region.  The copy
-// is ordered on the stream after any earlier call's kernels that read the
+// Stage d, a^2, 1/a^2 (in T and in double) into the params region, followed
+// with drift by the operand tables of A (in T and in double).  The copy is
+// ordered on the stream after any earlier call's kernels that read the
 // region, and completes before the host buffer goes out of scope.
 template <typename T>
-int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, char* region,
-                 hipStream_t st, const T** dT, const double** dD) {
+int stage_params(const hj_h_params* H, const hj_j_params* J, int n, const Shape& s,
+                 char* region, hipStream_t st, const T** dT, const double** dD,
+                 const T** aT, const double** aD) {
+  const int npad = s.npad();
   HostParams<T> pt = host_params<T>(H, J, n, npad);
   HostParams<double> pd = host_params<double>(H, J, n, npad);
-  std::vector<char> buf((size_t)npad * 3 * (sizeof(T) + 8));
+  const size_t plen = (size_t)npad * 3 * (sizeof(T) + 8);
+  const size_t tlen = s.dr ? drift_table_len(s.npl) : 0;
+  std::vector<char> buf(plen + tlen * (sizeof(T) + 8));
   char* q = buf.data();
   std::memcpy(q, pt.d.data(), npad * sizeof(T));
   std::memcpy(q + npad * sizeof(T), pt.a2.data(), npad * sizeof(T));
@@ -210,10 +257,18 @@ int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, ch
   std::memcpy(q2, pd.d.data(), npad * 8);
   std::memcpy(q2 + npad * 8, pd.a2.data(), npad * 8);
   std::memcpy(q2 + 2 * npad * 8, pd.ia2.data(), npad * 8);
+  if (tlen) {
+    const std::vector<double> t64 = drift_table<double>(H->A, n, s.npl);
+    const std::vector<T> tT = drift_table<T>(H->A, n, s.npl);
+    std::memcpy(q + plen, t64.data(), tlen * 8);
+    std::memcpy(q + plen + tlen * 8, tT.data(), tlen * sizeof(T));
+  }
   HJ_HIP(hipMemcpyAsync(region, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
   HJ_HIP(hipStreamSynchronize(st));
   *dT = reinterpret_cast<const T*>(region);
   *dD = reinterpret_cast<const double*>(region + 3 * npad * sizeof(T));
+  *aD = tlen ? reinterpret_cast<const double*>(region + plen) : nullptr;
+  *aT = tlen ? reinterpret_cast<const T*>(region + plen + tlen * 8) : nullptr;
   return HJ_OK;
 }
 
@@ -221,6 +276,17 @@ int stage_params(const hj_h_params* H, const hj_j_params* J, int n, int npad, ch
 template <typename T>
 hipError_t dispatch_solve(const Shape& s, int mk, const hj::SolveArgs<T>& A, int mode,
                           int64_t grid_groups, hipStream_t st) {
+  if (s.dr) {
+#define HJ_DCASE(NPL)                                                                         \
+  if (s.npl == NPL)                                                                           \
+    return mk == HJ_M_TANH ? hj::launch_solve<hj::Cfg<T, NPL, 4, HJ_M_TANH, true>>(          \
+                                 A, mode, grid_groups, st)                                    \
+                           : hj::launch_solve<hj::Cfg<T, NPL, 4, HJ_M_RAT, true>>(           \
+                                 A, mode, grid_groups, st);
+    HJ_FOR_EACH_DRIFT_NPL(HJ_DCASE)
+#undef HJ_DCASE
+    return hipErrorInvalidValue;
+  }
 #define HJ_CASE(NPL, LPT)                                                                   \
   if (s.npl == NPL && s.lpt == LPT)                                                         \
     return mk == HJ_M_TANH                                                                  \
@@ -233,6 +299,16 @@ hipError_t dispatch_solve(const Shape& s, int mk, const hj::SolveArgs<T>& A, int
 
 template <typename T>
 int64_t dispatch_resident(const Shape& s, int mk, int mode) {
+  if (s.dr) {
+#define HJ_DCASE(NPL)                                                                \
+  if (s.npl == NPL)                                                                  \
+    return mk == HJ_M_TANH                                                           \
+               ? hj::resident_groups<hj::Cfg<T, NPL, 4, HJ_M_TANH, true>>(mode)      \
+               : hj::resident_groups<hj::Cfg<T, NPL, 4, HJ_M_RAT, true>>(mode);
+    HJ_FOR_EACH_DRIFT_NPL(HJ_DCASE)
+#undef HJ_DCASE
+    return 0;
+  }
 #define HJ_CASE(NPL, LPT)                                                 \
   if (s.npl == NPL && s.lpt == LPT)                                       \
     return mk == HJ_M_TANH                                                \
@@ -256,6 +332,15 @@ int64_t schedule_groups(const Shape& s, int mk, int mode, int sched, int64_t nta
 
 template <typename T>
 hipError_t dispatch_eval(const Shape& s, int mk, const hj::EvalArgs<T>& A, hipStream_t st) {
+  if (s.dr) {
+#define HJ_DCASE(NPL)                                                                        \
+  if (s.npl == NPL)                                                                          \
+    return mk == HJ_M_TANH ? hj::launch_eval<hj::Cfg<T, NPL, 4, HJ_M_TANH, true>>(A, st)     \
+                           : hj::launch_eval<hj::Cfg<T, NPL, 4, HJ_M_RAT, true>>(A, st);
+    HJ_FOR_EACH_DRIFT_NPL(HJ_DCASE)
+#undef HJ_DCASE
+    return hipErrorInvalidValue;
+  }
 #define HJ_CASE(NPL, LPT)                                                               \
   if (s.npl == NPL && s.lpt == LPT)                                                     \
     return mk == HJ_M_TANH ? hj::launch_eval<hj::Cfg<T, NPL, LPT, HJ_M_TANH>>(A, st)    \
@@ -265,14 +350,26 @@ hipError_t dispatch_eval(const Shape& s, int mk, const hj::EvalArgs<T>& A, hipSt
   return hipErrorInvalidValue;
 }
 
+// The lane shape of a problem, or an error naming what is not compiled.
+int shape_for(const hj_h_params* H, int n, int lpt, Shape& s) {
+  const bool drift = H->A != nullptr;
+  if (pick_shape(n, lpt, drift, s)) return HJ_OK;
+  if (drift)
+    return fail(HJ_EUNSUPPORTED, "the drift kernels take n <= " +
+                                     std::to_string(4 * hj::kDriftNpl[2]) +
+                                     " and 4 lanes per task (n = " + std::to_string(n) +
+                                     ", lanes_per_task = " + std::to_string(lpt) + ")");
+  return fail(HJ_EUNSUPPORTED, "no kernel with " + std::to_string(lpt) +
+                                   " lanes per task for n = " + std::to_string(n));
+}
+
 template <typename T>
 int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B, int n,
             double t, int nsteps, const hj_guesses* gs, const hj_opts* o, double* out_u,
             void* out_argopt, int32_t* out_cert, const hj_slot_diag* diag) {
   Shape s{};
-  if (!pick_shape(n, o->lanes_per_task, s))
-    return fail(HJ_EUNSUPPORTED, "no kernel with " + std::to_string(o->lanes_per_task) +
-                                     " lanes per task for n = " + std::to_string(n));
+  int rc = shape_for(H, n, o->lanes_per_task, s);
+  if (rc) return rc;
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
   const int64_t ntask = B * (int64_t)gs->G;
@@ -283,18 +380,20 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   if ((size_t)B * gs->G * s.lpt > (size_t)UINT32_MAX * 128)
     return fail(HJ_EINVAL, "B * G too large for one launch");
   void* ws = nullptr;
-  int rc = get_workspace(o, WL.total, &ws);
+  rc = get_workspace(o, WL.total, &ws);
   if (rc) return rc;
   char* base = static_cast<char*>(ws);
   hipStream_t st = static_cast<hipStream_t>(o->stream);
-  const T* dT = nullptr;
-  const double* dD = nullptr;
-  rc = stage_params<T>(H, J, n, npad, base + WL.params, st, &dT, &dD);
+  const T *dT = nullptr, *aT = nullptr;
+  const double *dD = nullptr, *aD = nullptr;
+  rc = stage_params<T>(H, J, n, s, base + WL.params, st, &dT, &dD, &aT, &aD);
   if (rc) return rc;
 
   hj::SolveArgs<T> A;
   A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT, npad);
   A.P64 = make_problem<double>(H, J, n, t, nsteps, o->formula, o->quad, dD, npad);
+  A.P.aop = aT;
+  A.P64.aop = aD;
   A.x = static_cast<const T*>(x);
   A.guesses = static_cast<const T*>(gs->init);
   A.B = B;
@@ -352,24 +451,24 @@ int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B,
            double t, int nsteps, const void* v, int G, const hj_opts* o, double* out_phi,
            void* out_yN, double* out_rho, void* out_gv, void* out_gx) {
   Shape s{};
-  if (!pick_shape(n, o->lanes_per_task, s))
-    return fail(HJ_EUNSUPPORTED, "no kernel with " + std::to_string(o->lanes_per_task) +
-                                     " lanes per task for n = " + std::to_string(n));
+  int rc = shape_for(H, n, o->lanes_per_task, s);
+  if (rc) return rc;
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
   const bool grad = out_gv || out_gx;
   WsLayout WL = layout(s, n, B, G, nsteps, o->dtype, o->mode, K, grad, false);
   void* ws = nullptr;
-  int rc = get_workspace(o, WL.total, &ws);
+  rc = get_workspace(o, WL.total, &ws);
   if (rc) return rc;
   char* base = static_cast<char*>(ws);
   hipStream_t st = static_cast<hipStream_t>(o->stream);
-  const T* dT = nullptr;
-  const double* dD = nullptr;
-  rc = stage_params<T>(H, J, n, npad, base + WL.params, st, &dT, &dD);
+  const T *dT = nullptr, *aT = nullptr;
+  const double *dD = nullptr, *aD = nullptr;
+  rc = stage_params<T>(H, J, n, s, base + WL.params, st, &dT, &dD, &aT, &aD);
   if (rc) return rc;
   hj::EvalArgs<T> A;
   A.P = make_problem<T>(H, J, n, t, nsteps, o->formula, o->quad, dT, npad);
+  A.P.aop = aT;
   A.x = static_cast<const T*>(x);
   A.v = static_cast<const T*>(v);
   A.B = B;
@@ -466,7 +565,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
   std::vector<LaunchGroup> lg;
   for (int i = 0; i < n_inst; ++i) {
     Shape s{};
-    if (!pick_shape(inst[i].n, o->lanes_per_task, s))
+    if (!pick_shape(inst[i].n, o->lanes_per_task, false, s))
       return fail(HJ_EUNSUPPORTED, "no kernel shape for instance " + std::to_string(i));
     const int mk = kernel_mk(&inst[i].H);
     auto it = std::find_if(lg.begin(), lg.end(), [&](const LaunchGroup& g) {
@@ -688,13 +787,18 @@ int32_t hj_eval(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j
 size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const hj_opts* opts) {
   if (n < 1 || n > HJ_MAX_N || B < 0 || G < 1 || nsteps < 1) return 0;
   hj_opts o = opts ? *opts : default_opts();
-  Shape s{};
-  if (!pick_shape(n, o.lanes_per_task, s)) return 0;
   const int K = std::max(1, std::min(o.ckpt_K, nsteps));
-  // the larger of what hj_solve and hj_eval (with gradients) need
-  WsLayout a = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, false, true);
-  WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
-  return std::max(a.total, b.total);
+  // the largest of what hj_solve and hj_eval (with gradients) need, with or
+  // without a drift matrix
+  size_t need = 0;
+  for (int drift = 0; drift < 2; ++drift) {
+    Shape s{};
+    if (!pick_shape(n, o.lanes_per_task, drift != 0, s)) continue;
+    WsLayout a = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, false, true);
+    WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
+    need = std::max(need, std::max(a.total, b.total));
+  }
+  return need;
 }
 
 int32_t hj_batch_plan(int32_t H_kind, int32_t J_kind, const hj_instance* inst, int32_t n_inst,
@@ -716,6 +820,9 @@ int32_t hj_batch_plan(int32_t H_kind, int32_t J_kind, const hj_instance* inst, i
       return fail(HJ_EINVAL, "instance " + std::to_string(i) + ": bad G or R_max");
     if (!I.x || !I.guesses.init || !I.out_u || !I.out_argopt || !I.out_cert)
       return fail(HJ_EINVAL, "instance " + std::to_string(i) + ": missing arrays");
+    if (I.H.A)
+      return fail(HJ_EUNSUPPORTED,
+                  "instance " + std::to_string(i) + ": batched plans take no drift matrix");
   }
   hj_batch_plan_s* plan = new hj_batch_plan_s();
   rc = o.dtype == HJ_F64 ? plan_t<double>(inst, n_inst, &o, plan)

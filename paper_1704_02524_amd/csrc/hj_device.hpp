@@ -3,11 +3,18 @@
 // action quadrature, the discrete adjoint, and wave-level reductions.
 //
 // Layout: one "task" is one (query point, guess slot).  A task is held by LPT
-// adjacent lanes of a wavefront; lane `sub` of the group owns the NPL vector
-// components sub*NPL .. sub*NPL+NPL-1 of gamma, p, v, ... in registers
-// (padding components carry d = 0, x = v = 0 and stay exactly zero).  Sums
-// over components are butterfly reductions inside the group, so every lane of
-// a group holds bit-identical scalars and takes identical branches.
+// lanes of a wavefront, each owning NPL vector components of gamma, p, v, ...
+// in registers (padding components carry d = 0, x = v = 0 and stay exactly
+// zero).  Two lane layouts exist:
+//  * adjacent: the task's lanes are LPT neighbouring lanes, and lane `sub`
+//    owns components sub*NPL .. sub*NPL+NPL-1;
+//  * matrix-core (linear drift): 16 tasks per wave, task j on lanes
+//    j, j+16, j+32, j+48, lane `sub` (= lane / 16) owning components
+//    4k + sub.  This is the operand layout of the 16x16x4 MFMA, so A gamma
+//    and A^T p for the 16 tasks of a wave are MFMA chains with no data
+//    movement (see matvec2).
+// Sums over components are butterfly reductions inside the group, so every
+// lane of a group holds bit-identical scalars and takes identical branches.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -116,6 +123,49 @@ template <int LPT, typename T> __device__ __forceinline__ T gmax(T v) {
   return v;
 }
 
+// Sum / max over the four 16-lane rows of a wave (the matrix-core layout).
+// gfx950's permlane32 swap of a register with itself gives every lane the
+// values of rows {0,1} and of rows {2,3} at its position; permlane16 gives
+// rows {0,2} and {1,3}.  Combining the pair in a fixed order leaves the same
+// bits in all four lanes of a task.
+template <int HALF> __device__ __forceinline__ void xrow_u(unsigned v, unsigned& a, unsigned& b) {
+  if constexpr (HALF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    a = r[0];
+    b = r[1];
+  }
+}
+template <int HALF> __device__ __forceinline__ void xrow(float v, float& a, float& b) {
+  unsigned ua, ub;
+  xrow_u<HALF>(__builtin_bit_cast(unsigned, v), ua, ub);
+  a = __builtin_bit_cast(float, ua);
+  b = __builtin_bit_cast(float, ub);
+}
+template <int HALF> __device__ __forceinline__ void xrow(double v, double& a, double& b) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  unsigned la, lb, ha, hb;
+  xrow_u<HALF>((unsigned)u, la, lb);
+  xrow_u<HALF>((unsigned)(u >> 32), ha, hb);
+  a = __builtin_bit_cast(double, ((unsigned long long)ha << 32) | la);
+  b = __builtin_bit_cast(double, ((unsigned long long)hb << 32) | lb);
+}
+template <typename T> __device__ __forceinline__ T rsum4(T v) {
+  T a, b;
+  xrow<32>(v, a, b);
+  xrow<16>(a + b, a, b);
+  return a + b;
+}
+template <typename T> __device__ __forceinline__ T rmax4(T v) {
+  T a, b;
+  xrow<32>(v, a, b);
+  xrow<16>(nanmax(a, b), a, b);
+  return nanmax(a, b);
+}
+
 // Sum of NPL terms as a balanced tree (short dependency chains).
 template <int NPL, typename T> __device__ __forceinline__ T tree_sum(const T (&a)[NPL]) {
   if constexpr (NPL == 1) {
@@ -137,13 +187,53 @@ template <int NPL, typename T> __device__ __forceinline__ T tree_sum(const T (&a
 // ---------------------------------------------------------------------------
 // T: arithmetic type; NPL: components per lane; LPT: lanes per task;
 // MK: speed profile (HJ_M_TANH, or HJ_M_RAT which also serves HJ_M_CONST
-// with kappa = 0: c = 1 and c' = c'' = 0 exactly).
-template <typename T_, int NPL_, int LPT_, int MK_> struct Cfg {
+// with kappa = 0: c = 1 and c' = c'' = 0 exactly); DR: linear drift
+// <A x, p> in H, on the matrix-core layout (LPT = 4, NPL a multiple of 4).
+template <typename T_, int NPL_, int LPT_, int MK_, bool DR_ = false> struct Cfg {
   using T = T_;
   static constexpr int NPL = NPL_;
   static constexpr int LPT = LPT_;
   static constexpr int MK = MK_;
+  static constexpr bool DR = DR_;
+  static_assert(!DR || (LPT == 4 && NPL % 4 == 0), "drift layout: 4 lanes, NPL % 4 == 0");
+  // vector component held in slot k of lane `sub`
+  static __device__ __forceinline__ int comp(int sub, int k) {
+    return DR ? k * 4 + sub : sub * NPL + k;
+  }
+  // lane's index within its task group, and the task of a global lane
+  static __device__ __forceinline__ int sub_of(unsigned tid) {
+    return DR ? (int)((tid & 63) >> 4) : (int)(tid % LPT);
+  }
+  static __device__ __forceinline__ int64_t task_of(size_t lane) {
+    return DR ? (int64_t)((lane >> 6) * 16 + (lane & 15)) : (int64_t)(lane / LPT);
+  }
+  // lane (within the wave) of the group member with sub == 0
+  static __device__ __forceinline__ int leader(unsigned tid, int sub) {
+    return DR ? (int)(tid & 15) : (int)(tid % 64) - sub;
+  }
+  // elements of the MFMA operand table of A and A^T: [2][NPL/4][NPL][64]
+  static constexpr int kDriftTable = DR ? 2 * (NPL / 4) * NPL * 64 : 0;
 };
+
+// Sum / max over the lanes of a task group.
+template <class C, typename T> __device__ __forceinline__ T csum(T v) {
+  if constexpr (C::DR) return rsum4(v);
+  else return gsum<C::LPT>(v);
+}
+template <class C, typename T> __device__ __forceinline__ T cmax(T v) {
+  if constexpr (C::DR) return rmax4(v);
+  else return gmax<C::LPT>(v);
+}
+
+// Branch condition for a block of work that needs all lanes of the wave: the
+// matrix-core kernels run every MFMA with the whole wave active (an MFMA
+// reads its matrix operand from all 64 lanes), so a block that some task
+// needs runs on every lane and the other tasks discard its results.  Other
+// layouts branch per lane.
+template <class C> __device__ __forceinline__ bool wave_if(bool p) {
+  if constexpr (C::DR) return __builtin_amdgcn_ballot_w64(p) != 0;
+  else return p;
+}
 
 // problem description, in the arithmetic type T
 template <typename T> struct Problem {
@@ -156,6 +246,7 @@ template <typename T> struct Problem {
   const T* d;    // [npad] kinetic weights, 0 in padding
   const T* a2;   // [npad] a_i^2, 1 in padding
   const T* ia2;  // [npad] 1 / a_i^2, 1 in padding
+  const T* aop;  // drift: MFMA operand table of A and A^T (Cfg::kDriftTable), or null
 };
 
 // Per-lane copy of the component parameters (uniform across the wave when
@@ -163,15 +254,68 @@ template <typename T> struct Problem {
 template <class C> struct LaneParams {
   using T = typename C::T;
   T d[C::NPL], a2[C::NPL], ia2[C::NPL];
+  const T* aop;  // drift operand table (LDS or global), matrix-core layout only
   __device__ __forceinline__ void load(const Problem<T>& P, int sub) {
 #pragma unroll
     for (int k = 0; k < C::NPL; ++k) {
-      d[k] = P.d[sub * C::NPL + k];
-      a2[k] = P.a2[sub * C::NPL + k];
-      ia2[k] = P.ia2[sub * C::NPL + k];
+      d[k] = P.d[C::comp(sub, k)];
+      a2[k] = P.a2[C::comp(sub, k)];
+      ia2[k] = P.ia2[C::comp(sub, k)];
     }
+    aop = P.aop;
   }
 };
+
+// ---------------------------------------------------------------------------
+// linear drift on the matrix cores
+// ---------------------------------------------------------------------------
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dvec4 mfma4(double a, double b, dvec4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ fvec4 mfma4(float a, float b, fvec4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { using type = dvec4; };
+template <> struct Vec4<float> { using type = fvec4; };
+
+// ya = Ma xa and yb = Mb xb for the 16 tasks of the wave, with Ma, Mb in
+// {A, A^T} (mat index 0 = A, 1 = A^T).  One 16x16x4 MFMA multiplies the 16x4
+// block (ib, kb) of M by the 4 x 16 block of inputs whose row `sub` is slot
+// kb of the lanes of each task, which is where the layout keeps component
+// 4 kb + sub.  The operand table holds, per lane, the element of each block
+// that lane supplies; its host-side row order makes result register r of row
+// block ib land in slot 4 ib + r of the lane owning the component.  The two
+// products are interleaved as independent accumulation chains.
+template <class C>
+__device__ __forceinline__ void matvec2(const typename C::T* aop, int mat_a,
+                                        const typename C::T (&xa)[C::NPL],
+                                        typename C::T (&ya)[C::NPL], int mat_b,
+                                        const typename C::T (&xb)[C::NPL],
+                                        typename C::T (&yb)[C::NPL]) {
+  using T = typename C::T;
+  using V = typename Vec4<T>::type;
+  constexpr int NPL = C::NPL, NB = NPL / 4;
+  const int l = threadIdx.x & 63;
+  const T* pa = aop + mat_a * (NB * NPL * 64) + l;
+  const T* pb = aop + mat_b * (NB * NPL * 64) + l;
+#pragma unroll
+  for (int ib = 0; ib < NB; ++ib) {
+    V ca = {T(0), T(0), T(0), T(0)}, cb = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int kb = 0; kb < NPL; ++kb) {
+      ca = mfma4(pa[(ib * NPL + kb) * 64], xa[kb], ca);
+      cb = mfma4(pb[(ib * NPL + kb) * 64], xb[kb], cb);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ya[4 * ib + r] = ca[r];
+      yb[4 * ib + r] = cb[r];
+    }
+  }
+}
 
 // m = c^e and its derivatives in r = |gamma|^2.
 template <class C, bool NEED2>
@@ -213,9 +357,9 @@ __device__ __forceinline__ T integrand(const Problem<T>& P, T r, T q, T m, T m1)
 }
 
 // ---------------------------------------------------------------------------
-// RK4 in reversed time: y' = f(y), f(gamma, p) = (-m D p, (q m' + w) gamma)
-// (no drift).  NT independent trajectories are advanced together so their
-// instruction streams interleave.
+// RK4 in reversed time: y' = f(y), f(gamma, p) = (-(A gamma + m D p),
+// A^T p + (q m' + w) gamma) (the A terms with drift only).  NT independent
+// trajectories are advanced together so their instruction streams interleave.
 // ---------------------------------------------------------------------------
 
 // Sum of a[k] * b[k] over the lane's components as two interleaved FMA
@@ -250,8 +394,8 @@ __device__ __forceinline__ void reduce_rq(const typename C::T (&G)[NT][C::NPL],
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    r[t] = gsum<C::LPT>(r[t]);
-    q[t] = gsum<C::LPT>(q[t]);
+    r[t] = csum<C>(r[t]);
+    q[t] = csum<C>(q[t]);
   }
 }
 template <class C, int NT>
@@ -272,6 +416,8 @@ __device__ __forceinline__ void reduce_rq(const typename C::T (&G)[NT][C::NPL],
 // the accumulator y + h/6 (K1 + 2 K2 + 2 K3 + K4) and the next stage state
 // Y' = y + c h K with scalar coefficients, so each component costs seven
 // FP64 operations per stage (D p, two reduction FMAs, four update FMAs).
+// With drift, A G and A^T P come from the matrix cores and enter the same
+// updates through one more FMA each.
 template <class C, int NT, bool QUAD>
 __device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const LaneParams<C>& L,
                                          typename C::T (&g)[NT][C::NPL],
@@ -293,6 +439,11 @@ __device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const 
   }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
+    T AG[NT][NPL], ATP[NT][NPL];  // drift: A G and A^T P
+    if constexpr (C::DR) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) matvec2<C>(L.aop, 0, G[t], AG[t], 1, Pp[t], ATP[t]);
+    }
     reduce_rq<C, NT>(G, Pp, L, r, q, dp);
 #pragma unroll
     for (int t = 0; t < NT; ++t) speed<C, false>(P, r[t], m[t], m1[t], m2[t]);
@@ -306,11 +457,19 @@ __device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const 
       const T gn_c = -(cn * m[t]), pn_c = cn * cx;  // next-stage coefficients
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
-        ag[t][k] = __builtin_fma(ag_c, dp[t][k], s == 0 ? g[t][k] : ag[t][k]);
-        ap[t][k] = __builtin_fma(ap_c, G[t][k], s == 0 ? p[t][k] : ap[t][k]);
+        T ag0 = s == 0 ? g[t][k] : ag[t][k], ap0 = s == 0 ? p[t][k] : ap[t][k];
+        T gb = g[t][k], pb = p[t][k];
+        if constexpr (C::DR) {
+          ag0 = __builtin_fma(-wb, AG[t][k], ag0);
+          ap0 = __builtin_fma(wb, ATP[t][k], ap0);
+          gb = __builtin_fma(-cn, AG[t][k], gb);
+          pb = __builtin_fma(cn, ATP[t][k], pb);
+        }
+        ag[t][k] = __builtin_fma(ag_c, dp[t][k], ag0);
+        ap[t][k] = __builtin_fma(ap_c, G[t][k], ap0);
         if (s < 3) {
-          Pp[t][k] = __builtin_fma(pn_c, G[t][k], p[t][k]);
-          G[t][k] = __builtin_fma(gn_c, dp[t][k], g[t][k]);
+          Pp[t][k] = __builtin_fma(pn_c, G[t][k], pb);
+          G[t][k] = __builtin_fma(gn_c, dp[t][k], gb);
         }
       }
     }
@@ -381,7 +540,7 @@ __device__ __forceinline__ void forward(const Problem<typename C::T>& P, const L
                                         typename C::T (*yN_g)[C::NPL] = nullptr,
                                         typename C::T (*yN_p)[C::NPL] = nullptr) {
   using T = typename C::T;
-  constexpr int NPL = C::NPL, LPT = C::LPT;
+  constexpr int NPL = C::NPL;
   T g[NT][NPL], p[NT][NPL], acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -423,7 +582,7 @@ __device__ __forceinline__ void forward(const Problem<typename C::T>& P, const L
         term += g[t][k] * g[t][k] * L.ia2[k];
         res = nanmax(res, dabs(p[t][k] - g[t][k] * L.ia2[k]));
       }
-      term = T(0.5) * gsum<LPT>(term) + P.j0;
+      term = T(0.5) * csum<C>(term) + P.j0;
     } else {
       T xv = T(0);
 #pragma unroll
@@ -432,10 +591,10 @@ __device__ __forceinline__ void forward(const Problem<typename C::T>& P, const L
         xv += x[k] * v[t][k];
         res = nanmax(res, dabs(g[t][k] - L.a2[k] * p[t][k]));
       }
-      term = T(0.5) * gsum<LPT>(term) - P.j0 - gsum<LPT>(xv);
+      term = T(0.5) * csum<C>(term) - P.j0 - csum<C>(xv);
     }
     phi[t] = term + acc[t];
-    rho[t] = gmax<LPT>(res);
+    rho[t] = cmax<C>(res);
     if (yN_g) {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
@@ -464,8 +623,8 @@ __device__ __forceinline__ StageScal<typename C::T> stage_scalars(
   T dp[C::NPL];
 #pragma unroll
   for (int k = 0; k < C::NPL; ++k) dp[k] = L.d[k] * Pp[k];
-  S.r = gsum<C::LPT>(dot2<C::NPL>(G, G));
-  S.q = gsum<C::LPT>(dot2<C::NPL>(dp, Pp));
+  S.r = csum<C>(dot2<C::NPL>(G, G));
+  S.q = csum<C>(dot2<C::NPL>(dp, Pp));
   speed<C, true>(P, S.r, S.m, S.m1, S.m2);
   return S;
 }
@@ -485,10 +644,11 @@ __device__ __forceinline__ void integrand_grad_coef(const Problem<T>& P, const S
 }
 
 // Vector-Jacobian product of f at a stage state, plus wb * grad(integrand):
-//   out_gamma = -2 m' <D p, kg> gamma + 2 q m'' <gamma, kp> gamma
+//   out_gamma = -A^T kg - 2 m' <D p, kg> gamma + 2 q m'' <gamma, kp> gamma
 //               + (q m' + w) kp + wb cg gamma
-//   out_p     = D (-m kg + 2 m' <gamma, kp> p + wb cp p)
-// (kg, kp) is read from and out is written to the same arrays.
+//   out_p     = A kp + D (-m kg + 2 m' <gamma, kp> p + wb cp p)
+// (the A terms with drift only).  (kg, kp) is read from and out is written
+// to the same arrays.
 template <class C>
 __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const LaneParams<C>& L,
                                           const typename C::T (&G)[C::NPL],
@@ -501,19 +661,31 @@ __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const
   T dp[NPL];
 #pragma unroll
   for (int k = 0; k < NPL; ++k) dp[k] = L.d[k] * Pp[k];
-  const T s1 = gsum<C::LPT>(dot2<NPL>(dp, kg));
-  const T s2 = gsum<C::LPT>(dot2<NPL>(G, kp));
+  const T s1 = csum<C>(dot2<NPL>(dp, kg));
+  const T s2 = csum<C>(dot2<NPL>(G, kp));
   T cg = T(0), cp = T(0);
   if (wb != T(0)) integrand_grad_coef(P, S, cg, cp);
   const T ag = T(-2) * S.m1 * s1 + T(2) * S.q * S.m2 * s2 + wb * cg;
   const T al = S.q * S.m1 + P.w;
   const T ap = T(2) * S.m1 * s2 + wb * cp;
+  if constexpr (C::DR) {
+    T ATk[NPL], Ak[NPL];
+    matvec2<C>(L.aop, 1, kg, ATk, 0, kp, Ak);
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
-    const T og = __builtin_fma(al, kp[k], ag * G[k]);
-    const T op = __builtin_fma(ap, dp[k], -S.m * (L.d[k] * kg[k]));
-    kg[k] = og;
-    kp[k] = op;
+    for (int k = 0; k < NPL; ++k) {
+      const T og = __builtin_fma(al, kp[k], __builtin_fma(ag, G[k], -ATk[k]));
+      const T op = __builtin_fma(ap, dp[k], __builtin_fma(-S.m, L.d[k] * kg[k], Ak[k]));
+      kg[k] = og;
+      kp[k] = op;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      const T og = __builtin_fma(al, kp[k], ag * G[k]);
+      const T op = __builtin_fma(ap, dp[k], -S.m * (L.d[k] * kg[k]));
+      kg[k] = og;
+      kp[k] = op;
+    }
   }
 }
 
@@ -537,12 +709,27 @@ __device__ __forceinline__ void reverse_step(const Problem<typename C::T>& P,
     const T cn = (s == 2) ? h : h2;
     const T cx = S[s].q * S[s].m1 + P.w;
     const T gn_c = -(cn * S[s].m), pn_c = cn * cx;  // as in rk4_step
+    if constexpr (C::DR) {
+      T AG[NPL], ATP[NPL];
+      if (s == 0)
+        matvec2<C>(L.aop, 0, g, AG, 1, p, ATP);
+      else
+        matvec2<C>(L.aop, 0, YG[s - 1], AG, 1, YP[s - 1], ATP);
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      const T gs = s ? YG[s - 1][k] : g[k];
-      const T ps = s ? YP[s - 1][k] : p[k];
-      YG[s][k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
-      YP[s][k] = __builtin_fma(pn_c, gs, p[k]);
+      for (int k = 0; k < NPL; ++k) {
+        const T gs = s ? YG[s - 1][k] : g[k];
+        const T ps = s ? YP[s - 1][k] : p[k];
+        YG[s][k] = __builtin_fma(gn_c, L.d[k] * ps, __builtin_fma(-cn, AG[k], g[k]));
+        YP[s][k] = __builtin_fma(pn_c, gs, __builtin_fma(cn, ATP[k], p[k]));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        const T gs = s ? YG[s - 1][k] : g[k];
+        const T ps = s ? YP[s - 1][k] : p[k];
+        YG[s][k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+        YP[s][k] = __builtin_fma(pn_c, gs, p[k]);
+      }
     }
     S[s + 1] = stage_scalars<C>(P, L, YG[s], YP[s]);
   }

@@ -14,21 +14,31 @@
 namespace hj {
 
 // load n-vector row into the lane's NPL components (0 beyond n)
-template <typename T, int NPL>
-__device__ __forceinline__ void load_row(const T* base, int n, int sub, T (&out)[NPL]) {
+template <class C>
+__device__ __forceinline__ void load_row(const typename C::T* base, int n, int sub,
+                                         typename C::T (&out)[C::NPL]) {
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
-    const int i = sub * NPL + k;
-    out[k] = (i < n) ? base[i] : T(0);
+  for (int k = 0; k < C::NPL; ++k) {
+    const int i = C::comp(sub, k);
+    out[k] = (i < n) ? base[i] : typename C::T(0);
   }
 }
-template <typename T, int NPL>
-__device__ __forceinline__ void store_row(T* base, int n, int sub, const T (&in)[NPL]) {
+template <class C>
+__device__ __forceinline__ void store_row(typename C::T* base, int n, int sub,
+                                          const typename C::T (&in)[C::NPL]) {
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) {
-    const int i = sub * NPL + k;
+  for (int k = 0; k < C::NPL; ++k) {
+    const int i = C::comp(sub, k);
     if (i < n) base[i] = in[k];
   }
+}
+
+// Copy the drift operand table into the workgroup's LDS (every thread of the
+// block takes part; the matrix-core kernels never leave before this point).
+template <class C>
+__device__ __forceinline__ void stage_drift(const typename C::T* src, typename C::T* dst) {
+  for (int i = threadIdx.x; i < C::kDriftTable; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -37,36 +47,46 @@ __device__ __forceinline__ void store_row(T* base, int n, int sub, const T (&in)
 template <class C>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C::T> A) {
   using T = typename C::T;
-  constexpr int NPL = C::NPL, LPT = C::LPT;
+  constexpr int NPL = C::NPL;
+  __shared__ T s_aop[C::DR ? C::kDriftTable : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int sub = threadIdx.x % LPT;
-  const int64_t task = (int64_t)(lane / LPT);
-  if (task >= A.B * A.G) return;
+  const int sub = C::sub_of(threadIdx.x);
+  int64_t task = C::task_of(lane);
+  // matrix-core kernels keep lanes past the last task as idle wave members
+  const bool live = task < A.B * A.G;
+  if constexpr (!C::DR) {
+    if (!live) return;
+  }
+  if (!live) task = 0;
   const int64_t b = task / A.G;
   const int n = A.P.n;
   LaneParams<C> L;
   L.load(A.P, sub);
+  if constexpr (C::DR) {
+    stage_drift<C>(A.P.aop, s_aop);
+    L.aop = s_aop;
+  }
   T x[NPL], v[1][NPL], phi[1], rho[1], yg[1][NPL], yp[1][NPL];
-  load_row<T, NPL>(A.x + b * n, n, sub, x);
-  load_row<T, NPL>(A.v + task * n, n, sub, v[0]);
+  load_row<C>(A.x + b * n, n, sub, x);
+  load_row<C>(A.v + task * n, n, sub, v[0]);
   const bool grad = (A.gv != nullptr) || (A.gx != nullptr);
   if (grad)
     forward<C, 1, true>(A.P, L, x, v, phi, rho, A.ck, A.stride, lane, A.K, yg, yp);
   else
     forward<C, 1, false>(A.P, L, x, v, phi, rho, nullptr, 0, 0, 1, yg, yp);
-  if (sub == 0) {
+  if (live && sub == 0) {
     A.phi[task] = (double)phi[0];
     if (A.rho) A.rho[task] = (double)rho[0];
   }
-  if (A.yN) {
-    store_row<T, NPL>(A.yN + task * 2 * n, n, sub, yg[0]);
-    store_row<T, NPL>(A.yN + task * 2 * n + n, n, sub, yp[0]);
+  if (live && A.yN) {
+    store_row<C>(A.yN + task * 2 * n, n, sub, yg[0]);
+    store_row<C>(A.yN + task * 2 * n + n, n, sub, yp[0]);
   }
   if (grad) {
     T gv[NPL], gx[NPL];
     backward<C>(A.P, L, x, v[0], A.ck, A.seg, A.stride, lane, A.K, gv, gx);
-    if (A.gv) store_row<T, NPL>(A.gv + task * n, n, sub, gv);
-    if (A.gx) store_row<T, NPL>(A.gx + task * n, n, sub, gx);
+    if (live && A.gv) store_row<C>(A.gv + task * n, n, sub, gv);
+    if (live && A.gx) store_row<C>(A.gx + task * n, n, sub, gx);
   }
 }
 
@@ -119,18 +139,18 @@ template <class C, bool MULTI> struct TaskCtx {
       xb = A.x + (task / A.G) * n;
       g0 = A.guesses + task * (int64_t)(A.R + 1) * n;
     }
-    load_row<T, C::NPL>(xb, P(A).n, sub, x);
+    load_row<C>(xb, P(A).n, sub, x);
   }
 };
 
 // Next task for a lane group: the group's leader takes an index from the
 // queue and the group shares it.
-template <int LPT>
+template <class C>
 __device__ __forceinline__ int64_t pop_task(unsigned long long* queue, int sub) {
   unsigned long long t = 0;
   if (sub == 0) t = atomicAdd(queue, 1ULL);
-  if (LPT > 1) {
-    const int leader = (int)(threadIdx.x % 64) - sub;
+  if (C::LPT > 1) {
+    const int leader = C::leader(threadIdx.x, sub);
     const int lo = __shfl((int)(t & 0xffffffffULL), leader, 64);
     const int hi = __shfl((int)(t >> 32), leader, 64);
     t = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
@@ -157,17 +177,22 @@ struct SlotBest {
   }
 };
 
-// Certificate and objective of a finished run, in FP64.  FP32 runs with the
+// Objective and residual of a finished attempt in FP64.  FP32 runs with the
 // FP64 certificate re-solve the characteristic in FP64 at the final v.
+// `ending` marks the lanes whose attempt ends now; on the matrix-core layout
+// the re-solve runs on the whole wave when any lane needs it.
 template <class C, bool MULTI>
-__device__ __forceinline__ void final_values(const SolveArgs<typename C::T>& A,
-                                             const TaskCtx<C, MULTI>& tc, int sub,
-                                             const typename C::T (&v)[C::NPL],
-                                             typename C::T phi, typename C::T rho,
-                                             double& phi64, double& rho64) {
+__device__ __forceinline__ void attempt_values(const SolveArgs<typename C::T>& A,
+                                               const TaskCtx<C, MULTI>& tc, int sub,
+                                               const typename C::T (&v)[C::NPL],
+                                               typename C::T phi, typename C::T rho, int status,
+                                               bool ending, double& phi64, double& rho64) {
+  phi64 = (double)phi;
+  rho64 = (status == HJ_ST_DIVERGED) ? __builtin_nan("") : (double)rho;
   if constexpr (sizeof(typename C::T) == 4) {
-    if (A.cert_fp64) {
-      using C64 = Cfg<double, C::NPL, C::LPT, C::MK>;
+    const bool need = ending && status != HJ_ST_DIVERGED;
+    if (A.cert_fp64 && wave_if<C>(need)) {
+      using C64 = Cfg<double, C::NPL, C::LPT, C::MK, C::DR>;
       const Problem<double>& P64 = tc.P64(A);
       LaneParams<C64> L64;
       L64.load(P64, sub);
@@ -178,29 +203,22 @@ __device__ __forceinline__ void final_values(const SolveArgs<typename C::T>& A,
         v64[0][k] = (double)v[k];
       }
       forward<C64, 1, false>(P64, L64, x64, v64, ph, rh);
-      phi64 = ph[0];
-      rho64 = rh[0];
-      return;
+      if (need) {
+        phi64 = ph[0];
+        rho64 = rh[0];
+      }
     }
   }
-  phi64 = (double)phi;
-  rho64 = (double)rho;
 }
 
-// Record the end of one attempt; returns true when the slot is finished.
+// Record the end of one attempt with its FP64 objective and residual;
+// returns true when the slot is finished.
 template <class C, bool MULTI>
 __device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A,
                                             const TaskCtx<C, MULTI>& tc, int sub, int64_t task,
-                                            const typename C::T (&v)[C::NPL], typename C::T phi,
-                                            typename C::T rho, int status, int it, int att,
+                                            const typename C::T (&v)[C::NPL], double phi64,
+                                            double rho64, int status, int it, int att,
                                             SlotBest& best) {
-  double phi64, rho64;
-  if (status == HJ_ST_DIVERGED) {
-    phi64 = (double)phi;
-    rho64 = __builtin_nan("");
-  } else {
-    final_values<C, MULTI>(A, tc, sub, v, phi, rho, phi64, rho64);
-  }
   best.iters += it;
   best.attempts = att + 1;
   const bool fin = (status != HJ_ST_DIVERGED) && isfinite(phi64);
@@ -212,7 +230,7 @@ __device__ __forceinline__ bool end_attempt(const SolveArgs<typename C::T>& A,
     best.status = status;
     const int n = tc.P(A).n;
     // slot records use the row stride A.P.n (the largest n of a batch)
-    store_row<typename C::T, C::NPL>(A.out.v + task * A.P.n, n, sub, v);
+    store_row<C>(A.out.v + task * A.P.n, n, sub, v);
   }
   return certified || (att + 1 > tc.R);
 }
@@ -227,7 +245,7 @@ __device__ __forceinline__ void write_slot(const SolveArgs<typename C::T>& A,
     T nanv[C::NPL];
 #pragma unroll
     for (int k = 0; k < C::NPL; ++k) nanv[k] = T(__builtin_nan(""));
-    store_row<T, C::NPL>(A.out.v + task * A.P.n, n, sub, nanv);
+    store_row<C>(A.out.v + task * A.P.n, n, sub, nanv);
   }
   if (sub != 0) return;
   if (A.out.phi) A.out.phi[task] = best.phi;
@@ -259,7 +277,7 @@ __device__ __forceinline__ int stop_status(const SolveArgs<typename C::T>& A,
   T vmax = T(0);
 #pragma unroll
   for (int k = 0; k < C::NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
-  vmax = gmax<C::LPT>(vmax);
+  vmax = cmax<C>(vmax);
   if (!isfinite(phi) || !(vmax <= A.v_max)) return HJ_ST_DIVERGED;
   if (smax < A.eps_step) return HJ_ST_CONVERGED;
   if (alpha < alpha_floor) return HJ_ST_STALLED;
@@ -271,7 +289,7 @@ __device__ __forceinline__ int stop_status(const SolveArgs<typename C::T>& A,
 template <class C>
 __device__ __forceinline__ int64_t next_task(const SolveArgs<typename C::T>& A, int sub) {
   if (!A.queue) return -1;
-  const int64_t t = pop_task<C::LPT>(A.queue, sub);
+  const int64_t t = pop_task<C>(A.queue, sub);
   return t < A.ntask ? t : -1;
 }
 
@@ -283,17 +301,26 @@ __device__ __forceinline__ int64_t next_task(const SolveArgs<typename C::T>& A, 
 template <class C>
 __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
-  constexpr int NPL = C::NPL, LPT = C::LPT;
+  constexpr int NPL = C::NPL;
+  __shared__ T s_aop[C::DR ? C::kDriftTable : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int sub = threadIdx.x % LPT;
-  int64_t task = (int64_t)(lane / LPT);
-  if (task >= A.ntask) return;
+  const int sub = C::sub_of(threadIdx.x);
+  int64_t task = C::task_of(lane);
+  // matrix-core kernels keep lanes without a task as idle wave members
+  bool live = task < A.ntask;
+  if constexpr (!C::DR) {
+    if (!live) return;
+  }
   TaskCtx<C, false> tc;
   tc.L.load(A.P, sub);
-  tc.bind(A, task, sub);
+  if constexpr (C::DR) {
+    stage_drift<C>(A.P.aop, s_aop);
+    tc.L.aop = s_aop;
+  }
+  tc.bind(A, live ? task : 0, sub);
   const int n = A.P.n;
   T v[NPL];
-  load_row<T, NPL>(tc.g0, n, sub, v);
+  load_row<C>(tc.g0, n, sub, v);
   SlotBest best;
   best.reset();
   int att = 0, it = 0, j = 0;
@@ -304,11 +331,18 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
     T va[2][NPL], fp[2], rp[2];
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
-      const bool on = !start && (sub * NPL + k == j);
+      const bool on = !start && (C::comp(sub, k) == j);
       va[0][k] = on ? v[k] + A.sigma : v[k];
       va[1][k] = on ? v[k] - A.sigma : v[k];
     }
     forward<C, 2, false>(A.P, tc.L, tc.x, va, fp, rp);
+    // trial step along coordinate j
+    const T gj = (fp[0] - fp[1]) / (T(2) * A.sigma);
+    const T step = alpha * gj;
+    T vt[1][NPL], ft[1], rt[1];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) vt[0][k] = (C::comp(sub, k) == j) ? v[k] - step : v[k];
+    if (wave_if<C>(!start)) forward<C, 1, false>(A.P, tc.L, tc.x, vt, ft, rt);
     int status = -1;
     if (start) {
       best.n_fwd += 1;
@@ -324,13 +358,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
       else if (A.max_iter == 0)
         status = HJ_ST_MAXITER;
     } else {
-      const T gj = (fp[0] - fp[1]) / (T(2) * A.sigma);
-      const T step = alpha * gj;
       smax = nanmax(smax, dabs(step));
-      T vt[1][NPL], ft[1], rt[1];
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) vt[0][k] = (sub * NPL + k == j) ? v[k] - step : v[k];
-      forward<C, 1, false>(A.P, tc.L, tc.x, vt, ft, rt);
       best.n_fwd += 3;
       if (accept_step(A, ft[0], phi, alpha * gj * gj)) {
 #pragma unroll
@@ -347,19 +375,29 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
         smax = T(0);
       }
     }
-    if (status >= 0) {
-      if (end_attempt<C, false>(A, tc, sub, task, v, phi, rho, status, it, att, best)) {
+    const bool ending = live && status >= 0;
+    double phi64, rho64;
+    attempt_values<C, false>(A, tc, sub, v, phi, rho, status, ending, phi64, rho64);
+    if (ending) {
+      if (end_attempt<C, false>(A, tc, sub, task, v, phi64, rho64, status, it, att, best)) {
         write_slot<C, false>(A, tc, sub, task, best);
         task = next_task<C>(A, sub);
-        if (task < 0) break;
-        tc.bind(A, task, sub);
-        best.reset();
         att = 0;
+        if (task < 0) {
+          if constexpr (!C::DR) break;
+          live = false;
+        } else {
+          tc.bind(A, task, sub);
+          best.reset();
+        }
       } else {
         ++att;
       }
-      load_row<T, NPL>(tc.g0 + (int64_t)att * n, n, sub, v);
+      load_row<C>(tc.g0 + (int64_t)att * n, n, sub, v);
       start = true;
+    }
+    if constexpr (C::DR) {
+      if (!wave_if<C>(live)) break;
     }
   }
 }
@@ -370,16 +408,26 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
 template <class C, bool MULTI>
 __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
-  constexpr int NPL = C::NPL, LPT = C::LPT;
+  constexpr int NPL = C::NPL;
+  static_assert(!(MULTI && C::DR), "batched instances carry no drift");
+  __shared__ T s_aop[C::DR ? C::kDriftTable : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const int sub = threadIdx.x % LPT;
-  int64_t task = (int64_t)(lane / LPT);
-  if (task >= A.ntask) return;
+  const int sub = C::sub_of(threadIdx.x);
+  int64_t task = C::task_of(lane);
+  // matrix-core kernels keep lanes without a task as idle wave members
+  bool live = task < A.ntask;
+  if constexpr (!C::DR) {
+    if (!live) return;
+  }
   TaskCtx<C, MULTI> tc;
   if constexpr (!MULTI) tc.L.load(A.P, sub);
-  tc.bind(A, task, sub);
+  if constexpr (C::DR) {
+    stage_drift<C>(A.P.aop, s_aop);
+    tc.L.aop = s_aop;
+  }
+  tc.bind(A, live ? task : 0, sub);
   T v[NPL], g[NPL];
-  load_row<T, NPL>(tc.g0, tc.P(A).n, sub, v);
+  load_row<C>(tc.g0, tc.P(A).n, sub, v);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) g[k] = T(0);
   SlotBest best;
@@ -401,8 +449,8 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
         gm = nanmax(gm, dabs(g[k]));
         vt[0][k] = v[k] - alpha * g[k];
       }
-      smax = alpha * gmax<LPT>(gm);
-      gg = gsum<LPT>(dot2<NPL>(g, g));
+      smax = alpha * cmax<C>(gm);
+      gg = csum<C>(dot2<NPL>(g, g));
     }
     forward<C, 1, true>(P, tc.L, tc.x, vt, ft, rt, A.ck, A.stride, lane, A.K);
     best.n_fwd += 1;
@@ -415,10 +463,15 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
     } else {
       alpha *= T(0.5);
     }
-    if (acc && isfinite(phi)) {
-      T gx[NPL];
-      backward<C>(P, tc.L, tc.x, v, A.ck, A.seg, A.stride, lane, A.K, g, gx);
-      best.n_bwd += 1;
+    const bool need_grad = acc && isfinite(phi);
+    if (wave_if<C>(need_grad)) {
+      T gt[NPL], gx[NPL];
+      backward<C>(P, tc.L, tc.x, v, A.ck, A.seg, A.stride, lane, A.K, gt, gx);
+      if (need_grad) {
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) g[k] = gt[k];
+        best.n_bwd += 1;
+      }
     }
     int status = -1;
     if (start) {
@@ -433,19 +486,29 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
       ++it;
       status = stop_status<C>(A, v, phi, smax, alpha, it);
     }
-    if (status >= 0) {
-      if (end_attempt<C, MULTI>(A, tc, sub, task, v, phi, rho, status, it, att, best)) {
+    const bool ending = live && status >= 0;
+    double phi64, rho64;
+    attempt_values<C, MULTI>(A, tc, sub, v, phi, rho, status, ending, phi64, rho64);
+    if (ending) {
+      if (end_attempt<C, MULTI>(A, tc, sub, task, v, phi64, rho64, status, it, att, best)) {
         write_slot<C, MULTI>(A, tc, sub, task, best);
         task = next_task<C>(A, sub);
-        if (task < 0) break;
-        tc.bind(A, task, sub);
-        best.reset();
         att = 0;
+        if (task < 0) {
+          if constexpr (!C::DR) break;
+          live = false;
+        } else {
+          tc.bind(A, task, sub);
+          best.reset();
+        }
       } else {
         ++att;
       }
-      load_row<T, NPL>(tc.g0 + (int64_t)att * tc.P(A).n, tc.P(A).n, sub, v);
+      load_row<C>(tc.g0 + (int64_t)att * tc.P(A).n, tc.P(A).n, sub, v);
       start = true;
+    }
+    if constexpr (C::DR) {
+      if (!wave_if<C>(live)) break;
     }
   }
 }
@@ -573,12 +636,17 @@ hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, int64_t gri
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (mode == HJ_CD_FD)
+  if (mode == HJ_CD_FD) {
     hipLaunchKernelGGL(k_solve_cd<C>, dim3((unsigned)grid), dim3(block), 0, st, A);
-  else if (A.inst)
-    hipLaunchKernelGGL((k_solve_gd<C, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
-  else
+  } else if (A.inst) {
+    if constexpr (C::DR) {
+      return hipErrorInvalidValue;  // batches carry no drift
+    } else {
+      hipLaunchKernelGGL((k_solve_gd<C, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
+    }
+  } else {
     hipLaunchKernelGGL((k_solve_gd<C, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
+  }
   return hipGetLastError();
 }
 
@@ -635,3 +703,13 @@ hipError_t launch_scatter_diag(const InstDesc<T>* inst, int n_inst, int64_t tota
 #define HJ_INSTANTIATE_BOTH(T, NPL, LPT) \
   HJ_INSTANTIATE(T, NPL, LPT, HJ_M_TANH) \
   HJ_INSTANTIATE(T, NPL, LPT, HJ_M_RAT)
+// The matrix-core (linear drift) instances of one NPL (4 lanes per task).
+#define HJ_INSTANTIATE_DRIFT_MK(T, NPL, MK)                                                  \
+  template hipError_t hj::launch_solve<hj::Cfg<T, NPL, 4, MK, true>>(                        \
+      const hj::SolveArgs<T>&, int, int64_t, hipStream_t);                                   \
+  template int64_t hj::resident_groups<hj::Cfg<T, NPL, 4, MK, true>>(int);                 \
+  template hipError_t hj::launch_eval<hj::Cfg<T, NPL, 4, MK, true>>(const hj::EvalArgs<T>&, \
+                                                                    hipStream_t);
+#define HJ_INSTANTIATE_DRIFT(T, NPL)              \
+  HJ_INSTANTIATE_DRIFT_MK(T, NPL, HJ_M_TANH)      \
+  HJ_INSTANTIATE_DRIFT_MK(T, NPL, HJ_M_RAT)

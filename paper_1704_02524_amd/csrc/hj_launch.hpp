@@ -111,6 +111,7 @@ hipError_t launch_scatter_diag(const InstDesc<T>* inst, int n_inst, int64_t tota
 // covers n.
 struct Shape {
   int npl, lpt;
+  bool dr = false;  // matrix-core layout with linear drift (lpt = 4)
   constexpr int npad() const { return npl * lpt; }
 };
 constexpr Shape kShapes[] = {
@@ -119,6 +120,9 @@ constexpr Shape kShapes[] = {
     {2, 2}, {8, 1}, {2, 4}, {10, 1}, {8, 2}, {4, 8}, {7, 16},
 };
 constexpr int kNumDefaultShapes = 10;
+// Components per lane of the linear-drift (matrix-core) instances; the
+// padded dimension 4 * NPL is a multiple of 16, the MFMA block size.
+constexpr int kDriftNpl[] = {4, 8, 16};
 
 }  // namespace hj
 
@@ -126,3 +130,4 @@ constexpr int kNumDefaultShapes = 10;
 #define HJ_FOR_EACH_SHAPE(X) \
   X(2, 1) X(4, 1) X(4, 2) X(5, 2) X(3, 4) X(4, 4) X(8, 4) X(8, 8) X(13, 8) X(16, 8) \
   X(2, 2) X(8, 1) X(2, 4) X(10, 1) X(8, 2) X(4, 8) X(7, 16)
+#define HJ_FOR_EACH_DRIFT_NPL(X) X(4) X(8) X(16)

@@ -215,7 +215,12 @@ def c3_drift_n32(B: int = 65536, seed: int = SEED_BASE + 3, dtype: int = F64) ->
         formula=LAX, quad=RK4AUG, x=x, guesses=guesses, mode=GD_ADJ, dtype=dtype,
         max_iter=200, alpha0=ALPHA_DEFAULT, eps_step=1e-12, cert_tol=1e-6, ckpt_K=16,
         seed=seed)
-    return _as_dtype(wl) if dtype == F32 else wl
+    if dtype == F32:
+        # the FP32 comparison run takes the step and certificate thresholds of
+        # the other FP32 workload (n = 100): FP32 descent cannot drive the
+        # residual to 1e-6
+        wl = _as_dtype(wl.with_(eps_step=1e-6, cert_tol=1e-4))
+    return wl
 
 
 def c4_lax_n100(B: int = 262144, seed: int = SEED_BASE + 4) -> Workload:

@@ -108,3 +108,21 @@ def test_workspace_size_grows_with_the_problem():
     big = L.hj_workspace_size(10, 4096, 16, 128, None)
     assert 0 < small < big
     assert L.hj_workspace_size(0, 16, 4, 128, None) == 0
+
+
+def test_drift_limits_are_reported():
+    """The linear-drift kernels run on the matrix-core layout (4 lanes per
+    task, n <= 64); other requests and non-finite drift entries are errors
+    raised before any device work."""
+    from paper_1704_02524_amd import workloads as W
+    wl = W.c3_drift_n32(B=2)
+    rc, msg = _call_solve(wl, lanes_per_task=2)
+    assert rc == -5 and "drift" in msg
+    big = W.c3_drift_n32(B=2).with_(n=65, A=np.eye(65) * 0.5, d=np.ones(65), a=np.ones(65),
+                                    x=np.zeros((2, 65)))
+    rc, msg = _call_solve(big)
+    assert rc == -5 and "drift" in msg
+    A = wl.A.copy()
+    A[3, 4] = np.inf
+    rc, msg = _call_solve(wl.with_(A=A))
+    assert rc == -1 and "finite" in msg
