@@ -1,14 +1,17 @@
 """Benchmark of the Lax / Hopf solver on one MI355X.
 
-One step = one hj_solve call over the whole workload: every (point, guess)
-slot runs its descent with restarts, the certificate, and the selection over
-guesses.  The headline workload is the n=10 Hopf problem (4096 points in
-[-3,3]^10, 16 guesses, 128 RK4 steps with the RK4-augmented quadrature,
-adjoint-gradient descent, 200 iterations, certificate tolerance 1e-8); the
-same workload is also run once with central-difference coordinate descent
-for the adjoint-vs-FD speedup.
+One step = one pass of the whole solve over the workload: every (point,
+guess) slot runs its descent with restarts, the certificate, and the
+selection over guesses (hj_solve; for the batched workload one replay of the
+captured plan).  The default workload is the n=10 Hopf problem (4096 points
+in [-3,3]^10, 16 guesses, 128 RK4 steps with the RK4-augmented quadrature,
+adjoint-gradient descent, 200 iterations, certificate tolerance 1e-8); it is
+also run once with central-difference coordinate descent for the
+adjoint-vs-FD speedup.  --workload selects the other configurations
+(n=32 linear drift in FP64 or FP32, n=100 FP32, n=2 Lax with coordinate
+descent, 64 batched uneven instances).
 
-Prints ONE JSON line (rank 0).  Progress goes to stderr.
+Prints ONE JSON line.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -25,31 +28,52 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "certified u(x,t) solves/sec at n=10,32; adjoint vs central-FD descent speedup"
-PEAK_FP64_VECTOR_TFLOPS = 78.6
+# MI355X published peaks (dense), TFLOP/s
+PEAK = {("alu", "f64"): 78.6, ("alu", "f32"): 157.3, ("mfma", "f64"): 78.6,
+        ("mfma", "f32"): 157.3}
+WORKLOADS = ("hopf_n10", "lax_n32_drift", "lax_n32_drift_f32", "lax_n100_f32", "lax_n2",
+             "batched", "batched_f32")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic work per unit (FMA = 2 flops, tanh or a division = 1), for
-# H without drift in dimension n:
+# Algorithmic work per unit (FMA = 2 flops, tanh or a division = 1) for
+# dimension n:
 #   one RK4 stage of the forward solve:  16 n + 16
 #   one stage of the adjoint sweep:      20 n + 14
+# and with a drift matrix A in addition
+#   forward stage: A gamma and A^T p (2 x 2 n^2) and their four updates (8 n)
+#   adjoint stage: A^T lambda_gamma and A lambda_p (2 x 2 n^2) and 4 n
 # A forward solve is N steps of 4 stages, an adjoint sweep N steps of 4
 # adjoint stages.  Recomputation inside the checkpointed adjoint is not
 # counted: it is overhead of the implementation, not work of the method.
-def fwd_flops(n, N):
-    return N * 4 * (16 * n + 16)
+def fwd_flops(n, N, drift=False):
+    return N * 4 * (16 * n + 16 + ((4 * n * n + 8 * n) if drift else 0))
 
 
-def adj_flops(n, N):
-    return N * 4 * (20 * n + 14)
+def adj_flops(n, N, drift=False):
+    return N * 4 * (20 * n + 14 + ((4 * n * n + 4 * n) if drift else 0))
 
 
 def algorithmic_flops(wl, slot_fwd, slot_bwd):
-    return float(slot_fwd.sum()) * fwd_flops(wl.n, wl.nsteps) + \
-        float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps)
+    dr = wl.A is not None
+    return float(slot_fwd.sum()) * fwd_flops(wl.n, wl.nsteps, dr) + \
+        float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps, dr)
+
+
+def _events(k):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(k)]
+    for a, b in evs:
+        # torch creates an event on its first record; the library then
+        # re-records the same events around its descent kernel
+        a.record()
+        b.record()
+    torch.cuda.synchronize()
+    return evs
 
 
 def run_gpu(wl, steps, warmup, label, cfg=None):
@@ -61,14 +85,7 @@ def run_gpu(wl, steps, warmup, label, cfg=None):
         out = hj.solve(wl, x, g, out=out, **(cfg or {}))
         torch.cuda.synchronize()
         log(f"{label}: warmup {i + 1}/{warmup} done")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
-    for a, b in evs:
-        # torch creates an event on its first record; the library then
-        # re-records the same events around its descent kernel
-        a.record()
-        b.record()
-    torch.cuda.synchronize()
+    evs = _events(steps)
     t0 = time.perf_counter()
     for i in range(steps):
         out = hj.solve(wl, x, g, out=out, events=evs[i], **(cfg or {}))
@@ -81,24 +98,95 @@ def run_gpu(wl, steps, warmup, label, cfg=None):
     return wall, kern_ms, host
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """The FP64 reference, single-threaded, on a prefix of the points with all
-    their guesses, until about budget_s seconds of work."""
+def run_batched(wls, steps, warmup):
+    """Replays of one captured plan; the events bracket the whole graph on
+    the stream it is launched on."""
+    import torch
+    from paper_1704_02524_amd import hj
+    plan = hj.BatchPlan(wls)
+    log(f"batched plan: {plan.info()}")
+    for i in range(warmup):
+        plan.run()
+        torch.cuda.synchronize()
+        log(f"batched: warmup {i + 1}/{warmup} done")
+    evs = _events(steps)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record()
+        outs = plan.run()
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    log(f"batched: {steps} steps, {wall * 1e3:.1f} ms/step, graph {np.mean(kern_ms):.1f} ms")
+    hosts = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    info = plan.info()
+    plan.free()
+    return wall, kern_ms, hosts, info
+
+
+def cpu_baseline(wls, budget_s=15.0):
+    """The FP64 reference, single-threaded, on points taken in turn from the
+    instances (a prefix of the points for one instance) with all their
+    guesses, until about budget_s seconds of work."""
     from oracle.oracle import Oracle, build
     build()
-    o = Oracle.from_workload(wl)
-    O = Oracle.opts_from_workload(wl)
+    oracles = [(Oracle.from_workload(w), Oracle.opts_from_workload(w)) for w in wls]
     t0 = time.perf_counter()
     n_pts = n_cert = 0
-    while time.perf_counter() - t0 < budget_s and n_pts < wl.B:
-        sub = wl.subset(n_pts, n_pts + 1)
+    nxt = [0] * len(wls)
+    i = 0
+    while time.perf_counter() - t0 < budget_s and any(nxt[j] < wls[j].B for j in range(len(wls))):
+        j = i % len(wls)
+        i += 1
+        if nxt[j] >= wls[j].B:
+            continue
+        sub = wls[j].subset(nxt[j], nxt[j] + 1)
+        nxt[j] += 1
+        o, O = oracles[j]
         r = o.solve(sub.x, sub.guesses, O, diag=False)
         n_cert += int(r["cert"][0] == 1)
         n_pts += 1
     dt = time.perf_counter() - t0
+    what = (f"first {n_pts} points of the same workload" if len(wls) == 1 else
+            f"{n_pts} points taken in turn from the {len(wls)} instances")
     return dict(value=n_cert / dt, unit="certified solves/s", cores=1, kind="oracle",
-                sample=f"first {n_pts} points of the same workload with all {wl.G} guesses "
-                       f"({dt:.1f} s, {n_cert} certified), FP64 reference, 1 thread")
+                sample=f"{what} with all their guesses ({dt:.1f} s, {n_cert} certified), "
+                       f"FP64 reference, 1 thread")
+
+
+def describe(wl):
+    from paper_1704_02524_amd import workloads as W
+    form = "Lax" if wl.formula == W.LAX else "Hopf"
+    quad = "RK4-augmented" if wl.quad == W.RK4AUG else "trapezoid"
+    mode = "adjoint gradient descent" if wl.mode == W.GD_ADJ else \
+        "central-FD coordinate descent"
+    lo, hi = float(wl.x.min()), float(wl.x.max())
+    drift = ", linear drift <Ax,p> (A on the matrix cores)" if wl.A is not None else ""
+    prec = "FP64" if wl.dtype == W.F64 else ("FP32 with FP64 certificate" if wl.cert_fp64
+                                             else "FP32")
+    return (f"{wl.name}: {form}, n={wl.n}{drift}, {wl.B} points U[{lo:.0f},{hi:.0f}]^n, "
+            f"{wl.G} guesses (+{wl.R_max} restarts), t={wl.t:g}, {wl.nsteps} RK4 steps, "
+            f"{quad} quadrature, {mode}, {wl.max_iter} iterations, certificate tol "
+            f"{wl.cert_tol:g}, {prec}")
+
+
+def build_workloads(name, points):
+    from paper_1704_02524_amd import workloads as W
+    if name == "hopf_n10":
+        return [W.c1_hopf_n10(B=points or 4096, mode=W.GD_ADJ)]
+    if name == "lax_n32_drift":
+        return [W.c3_drift_n32(B=points or 65536)]
+    if name == "lax_n32_drift_f32":
+        return [W.c3_drift_n32(B=points or 65536, dtype=W.F32)]
+    if name == "lax_n100_f32":
+        return [W.c4_lax_n100(B=points or 262144)]
+    if name == "lax_n2":
+        return [W.c0_lax_n2(B=points or 1024)]
+    if name in ("batched", "batched_f32"):
+        return W.c2_batched(dtype=W.F32 if name == "batched_f32" else W.F64,
+                            max_points=points)
+    raise ValueError(name)
 
 
 def main():
@@ -106,7 +194,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--points", type=int, default=4096)
+    ap.add_argument("--workload", choices=WORKLOADS, default="hopf_n10")
+    ap.add_argument("--points", type=int, default=None,
+                    help="query points (per instance for the batched workload)")
+    ap.add_argument("--cd-points", type=int, default=None,
+                    help="points of the central-FD comparison run (default: all)")
     ap.add_argument("--no-cd", action="store_true", help="skip the central-FD comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
@@ -122,14 +214,42 @@ def main():
     from paper_1704_02524_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    wl = W.c1_hopf_n10(B=args.points, mode=W.GD_ADJ)
-    log(f"workload {wl.name}: B={wl.B} G={wl.G} n={wl.n} N={wl.nsteps}")
-    cfg = {} if args.no_tune else tune.tune(wl, verbose=True)
-    log(f"launch configuration: {cfg or 'library default'}")
-    wall, kern, host = run_gpu(wl, args.steps, args.warmup, "adjoint GD", cfg)
-    n_cert = int((host["cert"] == 1).sum())
+    wls = build_workloads(args.workload, args.points)
+    wl = wls[0]
+    batched = len(wls) > 1
+    dtype = "f64" if wl.dtype == W.F64 else "f32"
+    bound = "mfma" if wl.A is not None else "alu"
+    peak = PEAK[(bound, dtype)]
+    if batched:
+        log(f"workload {args.workload}: {len(wls)} instances, "
+            f"{sum(w.B for w in wls)} points, {sum(w.B * w.G for w in wls)} tasks")
+        wall, kern, hosts, info = run_batched(wls, args.steps, args.warmup)
+        cfg = {"plan": info}
+        n_cert = int(sum((h["cert"] == 1).sum() for h in hosts))
+        flops = sum(algorithmic_flops(w, h["slot_fwd"], h["slot_bwd"])
+                    for w, h in zip(wls, hosts))
+        kernel = "k_solve_gd (batched launches of one graph)"
+        config = {
+            "workload": f"{args.workload}: {len(wls)} Hopf instances, n in "
+                        f"{sorted({w.n for w in wls})}, t~U[0.2,2], N in "
+                        f"{sorted({w.nsteps for w in wls})}, {sum(w.B for w in wls)} points "
+                        f"in total, {wl.G} guesses, adjoint gradient descent, one captured "
+                        f"graph, {dtype.upper()}",
+            "instances": len(wls), "points": int(sum(w.B for w in wls)), "guesses": wl.G,
+            "certified_points": n_cert,
+        }
+    else:
+        log(f"workload {wl.name}: B={wl.B} G={wl.G} n={wl.n} N={wl.nsteps}")
+        cfg = {} if args.no_tune else tune.tune(wl, verbose=True)
+        log(f"launch configuration: {cfg or 'library default'}")
+        mode_name = "adjoint GD" if wl.mode == W.GD_ADJ else "central-FD CD"
+        wall, kern, host = run_gpu(wl, args.steps, args.warmup, mode_name, cfg)
+        n_cert = int((host["cert"] == 1).sum())
+        flops = algorithmic_flops(wl, host["slot_fwd"], host["slot_bwd"])
+        kernel = "k_solve_gd" if wl.mode == W.GD_ADJ else "k_solve_cd"
+        config = {"workload": describe(wl), "points": wl.B, "guesses": wl.G, "n": wl.n,
+                  "nsteps": wl.nsteps, "certified_points": n_cert}
     value = n_cert / wall
-    flops = algorithmic_flops(wl, host["slot_fwd"], host["slot_bwd"])
     k_s = float(np.mean(kern)) / 1e3
     achieved = flops / k_s / 1e12
 
@@ -144,42 +264,41 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {
-            "workload": f"{wl.name}: Hopf, n={wl.n}, {wl.B} points U[-3,3]^n, {wl.G} "
-                        f"guesses N(0,I) (+2 restarts), t={wl.t}, {wl.nsteps} RK4 steps, "
-                        f"RK4-augmented quadrature, adjoint gradient descent, "
-                        f"{wl.max_iter} iterations, certificate tol {wl.cert_tol:g}",
-            "points": wl.B, "guesses": wl.G, "n": wl.n, "nsteps": wl.nsteps,
-            "certified_points": n_cert,
-        },
+        "config": config,
         "roofline": {
-            "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-            "kernel": "k_solve_gd", "launch": cfg, "kernel_ms": float(np.mean(kern)),
+            "bound": bound, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "kernel": kernel, "launch": cfg, "kernel_ms": float(np.mean(kern)),
             "algorithmic_flops_per_launch": flops,
         },
     }
-    if not args.no_cd:
+    if not batched and wl.mode == W.GD_ADJ and not args.no_cd:
         wcd = wl.with_(mode=W.CD_FD)
+        if args.cd_points:
+            wcd = wcd.subset(0, min(args.cd_points, wl.B))
         cfg_cd = {} if args.no_tune else tune.tune(wcd, tune_iters=2, verbose=True)
         log(f"launch configuration (CD): {cfg_cd or 'library default'}")
         wall_cd, kern_cd, host_cd = run_gpu(wcd, 1, 0, "central-FD CD", cfg_cd)
-        fin = (host["cert"] >= 0) & (host_cd["cert"] >= 0)
-        du = np.abs(host["u"][fin] - host_cd["u"][fin]) / np.maximum(1, np.abs(host["u"][fin]))
+        m = wcd.B
+        fin = (host["cert"][:m] >= 0) & (host_cd["cert"] >= 0)
+        du = np.abs(host["u"][:m][fin] - host_cd["u"][fin]) / \
+            np.maximum(1, np.abs(host["u"][:m][fin]))
         flops_cd = algorithmic_flops(wcd, host_cd["slot_fwd"], host_cd["slot_bwd"])
         result["cd_fd"] = {
+            "points": m,
             "ms_per_step": wall_cd * 1e3,
             "certified_points": int((host_cd["cert"] == 1).sum()),
             "value": int((host_cd["cert"] == 1).sum()) / wall_cd,
             "achieved_tflops": flops_cd / (kern_cd[0] / 1e3) / 1e12,
             "max_rel_u_diff_vs_adjoint": float(du.max(initial=0.0)),
         }
-        result["speedup_adjoint_vs_cd"] = wall_cd / wall
+        # time per point of the two descents (equal when all points are run)
+        result["speedup_adjoint_vs_cd"] = (wall_cd / m) / (wall / wl.B)
     if not args.no_cpu:
         log("CPU reference baseline ...")
-        result["cpu_baseline"] = cpu_baseline(wl)
+        result["cpu_baseline"] = cpu_baseline(wls)
         log(f"CPU: {result['cpu_baseline']['value']:.3f} certified solves/s")
     print(json.dumps(result), flush=True)
 

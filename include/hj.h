@@ -66,6 +66,7 @@ extern "C" {
 
 #define HJ_MAX_G    64      /* guesses per point                            */
 #define HJ_MAX_N   128      /* space dimension                              */
+#define HJ_MAX_N_DRIFT 64   /* space dimension with a drift matrix A        */
 
 enum { HJ_H_QUADRATIC = 0 };              /* H_kind: the family above       */
 enum { HJ_J_ELLIPSOID = 0 };              /* J_kind: ellipsoid g            */
@@ -85,7 +86,10 @@ typedef struct {
     double  s;            /* tanh scale (HJ_M_TANH), > 0                   */
     double  w;            /* potential 1/2 w |x|^2                         */
     const double *d;      /* host [n] kinetic weights (usually +-1)        */
-    const double *A;      /* host [n*n] row-major drift, or NULL           */
+    const double *A;      /* host [n*n] row-major drift (finite), or NULL.
+                             With A the kernels run on the matrix cores:
+                             n <= HJ_MAX_N_DRIFT, 4 lanes per task, not in
+                             batched plans (HJ_EUNSUPPORTED otherwise)     */
 } hj_h_params;
 
 typedef struct {
@@ -168,8 +172,10 @@ typedef struct {
  *   diag       optional per-slot outputs (NULL for none)
  * Selection: among certified slots the lowest objective, ties to the lowest
  * slot index.  B = 0 is a no-op.  Errors: HJ_EINVAL for n < 1, nsteps < 1,
- * t <= 0, G outside [1, HJ_MAX_G], R_max < 0, max_iter < 0, NULL arrays;
- * HJ_EUNSUPPORTED for n > HJ_MAX_N or an unknown H_kind / J_kind. */
+ * t <= 0, G outside [1, HJ_MAX_G], R_max < 0, max_iter < 0, NULL arrays,
+ * non-finite drift entries; HJ_EUNSUPPORTED for n > HJ_MAX_N, an unknown
+ * H_kind / J_kind, or a drift matrix with n > HJ_MAX_N_DRIFT or
+ * lanes_per_task other than 0 or 4. */
 int32_t hj_solve(int32_t H_kind, const hj_h_params *H, int32_t J_kind, const hj_j_params *J,
                  const void *x, int64_t B, int32_t n, double t, int32_t nsteps,
                  const hj_guesses *guesses, const hj_opts *opts,

@@ -356,7 +356,7 @@ int shape_for(const hj_h_params* H, int n, int lpt, Shape& s) {
   if (pick_shape(n, lpt, drift, s)) return HJ_OK;
   if (drift)
     return fail(HJ_EUNSUPPORTED, "the drift kernels take n <= " +
-                                     std::to_string(4 * hj::kDriftNpl[2]) +
+                                     std::to_string(HJ_MAX_N_DRIFT) +
                                      " and 4 lanes per task (n = " + std::to_string(n) +
                                      ", lanes_per_task = " + std::to_string(lpt) + ")");
   return fail(HJ_EUNSUPPORTED, "no kernel with " + std::to_string(lpt) +

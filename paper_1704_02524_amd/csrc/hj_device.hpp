@@ -249,21 +249,27 @@ template <typename T> struct Problem {
   const T* aop;  // drift: MFMA operand table of A and A^T (Cfg::kDriftTable), or null
 };
 
-// Per-lane copy of the component parameters (uniform across the wave when
-// LPT == 1, so the compiler keeps them in scalar registers).
+// Component parameters of a lane: the kinetic weights, used in every stage,
+// are held in registers (uniform across the wave when LPT == 1, so scalar
+// registers); the ellipsoid axes, used once per trajectory, are read from
+// memory where needed.
 template <class C> struct LaneParams {
   using T = typename C::T;
-  T d[C::NPL], a2[C::NPL], ia2[C::NPL];
-  const T* aop;  // drift operand table (LDS or global), matrix-core layout only
-  __device__ __forceinline__ void load(const Problem<T>& P, int sub) {
+  T d[C::NPL];
+  const T* a2p;   // [npad] a_i^2
+  const T* ia2p;  // [npad] 1 / a_i^2
+  const T* aop;   // drift operand table (LDS or global), matrix-core layout only
+  int sub;
+  __device__ __forceinline__ void load(const Problem<T>& P, int sub_) {
+    sub = sub_;
 #pragma unroll
-    for (int k = 0; k < C::NPL; ++k) {
-      d[k] = P.d[C::comp(sub, k)];
-      a2[k] = P.a2[C::comp(sub, k)];
-      ia2[k] = P.ia2[C::comp(sub, k)];
-    }
+    for (int k = 0; k < C::NPL; ++k) d[k] = P.d[C::comp(sub, k)];
+    a2p = P.a2;
+    ia2p = P.ia2;
     aop = P.aop;
   }
+  __device__ __forceinline__ T a2(int k) const { return a2p[C::comp(sub, k)]; }
+  __device__ __forceinline__ T ia2(int k) const { return ia2p[C::comp(sub, k)]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -503,26 +509,35 @@ __device__ __forceinline__ void node_integrand(const Problem<typename C::T>& P,
   }
 }
 
-// Checkpoint storage: structure-of-arrays, lane-contiguous.  Slot c of
-// component k of a lane lives at base[(c * 2 * NPL + k) * stride + lane].
+// Checkpoint storage, blocked by wavefront: the 2 NPL values of slot c of
+// the 64 lanes of wave w form one block of 2 NPL x 64 elements at block index
+// c * (stride / 64) + w, component-major inside (stride = lanes of the
+// arrays, a multiple of 64).  Loads and stores are coalesced across the wave
+// and the per-component offsets are small compile-time constants, so no
+// per-component address registers are needed.
+template <typename T, int NPL>
+__device__ __forceinline__ T* state_block(T* base, size_t stride, size_t lane, int c) {
+  const size_t blk = (size_t)c * (stride >> 6) + (lane >> 6);
+  return base + blk * (2 * NPL * 64) + (lane & 63);
+}
 template <typename T, int NPL>
 __device__ __forceinline__ void store_state(T* base, size_t stride, size_t lane, int c,
                                             const T (&g)[NPL], const T (&p)[NPL]) {
-  T* b = base + (size_t)c * 2 * NPL * stride + lane;
+  T* b = state_block<T, NPL>(base, stride, lane, c);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) {
-    b[(size_t)k * stride] = g[k];
-    b[(size_t)(NPL + k) * stride] = p[k];
+    b[k * 64] = g[k];
+    b[(NPL + k) * 64] = p[k];
   }
 }
 template <typename T, int NPL>
 __device__ __forceinline__ void load_state(const T* base, size_t stride, size_t lane, int c,
                                            T (&g)[NPL], T (&p)[NPL]) {
-  const T* b = base + (size_t)c * 2 * NPL * stride + lane;
+  const T* b = state_block<T, NPL>(const_cast<T*>(base), stride, lane, c);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) {
-    g[k] = b[(size_t)k * stride];
-    p[k] = b[(size_t)(NPL + k) * stride];
+    g[k] = b[k * 64];
+    p[k] = b[(NPL + k) * 64];
   }
 }
 
@@ -541,14 +556,16 @@ __device__ __forceinline__ void forward(const Problem<typename C::T>& P, const L
                                         typename C::T (*yN_p)[C::NPL] = nullptr) {
   using T = typename C::T;
   constexpr int NPL = C::NPL;
-  T g[NT][NPL], p[NT][NPL], acc[NT];
+  T g[NT][NPL], p[NT][NPL], acc[NT], xv[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     acc[t] = T(0);
+    xv[t] = T(0);
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       g[t][k] = x[k];
       p[t][k] = v[t][k];
+      if (P.formula == HJ_HOPF) xv[t] += x[k] * v[t][k];  // <x, v> of the Hopf objective
     }
   }
   const bool aug = (P.quad == HJ_RK4AUG);
@@ -579,19 +596,17 @@ __device__ __forceinline__ void forward(const Problem<typename C::T>& P, const L
     if (P.formula == HJ_LAX) {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
-        term += g[t][k] * g[t][k] * L.ia2[k];
-        res = nanmax(res, dabs(p[t][k] - g[t][k] * L.ia2[k]));
+        term += g[t][k] * g[t][k] * L.ia2(k);
+        res = nanmax(res, dabs(p[t][k] - g[t][k] * L.ia2(k)));
       }
       term = T(0.5) * csum<C>(term) + P.j0;
     } else {
-      T xv = T(0);
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
-        term += L.a2[k] * p[t][k] * p[t][k];
-        xv += x[k] * v[t][k];
-        res = nanmax(res, dabs(g[t][k] - L.a2[k] * p[t][k]));
+        term += L.a2(k) * p[t][k] * p[t][k];
+        res = nanmax(res, dabs(g[t][k] - L.a2(k) * p[t][k]));
       }
-      term = T(0.5) * csum<C>(term) - P.j0 - csum<C>(xv);
+      term = T(0.5) * csum<C>(term) - P.j0 - csum<C>(xv[t]);
     }
     phi[t] = term + acc[t];
     rho[t] = cmax<C>(res);
@@ -690,9 +705,11 @@ __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const
 }
 
 // Reverse sweep through one RK4 step from y_k = (g, p): lam holds d(obj)/d
-// y_{k+1} on entry and d(obj)/d y_k on exit (stage recomputation in registers).
+// y_{k+1} on entry and d(obj)/d y_k on exit.  This form recomputes the stage
+// states once and keeps them in registers; with drift they are not local to
+// a component (A mixes them), so the drift kernels use it.
 template <class C>
-__device__ __forceinline__ void reverse_step(const Problem<typename C::T>& P,
+__device__ __forceinline__ void reverse_step_stored(const Problem<typename C::T>& P,
                                              const LaneParams<C>& L,
                                              const typename C::T (&g)[C::NPL],
                                              const typename C::T (&p)[C::NPL], bool aug,
@@ -771,6 +788,114 @@ __device__ __forceinline__ void reverse_step(const Problem<typename C::T>& P,
   }
 }
 
+// Without drift, stage s + 1 of the RK4 step is, component by component,
+//   G_{s+1} = g - c_s h m_s d P_s,   P_{s+1} = p + c_s h (q_s m'_s + w) G_s,
+// so once the stage scalars are known every stage state follows from
+// (g, p) with a few FMAs per component.  This form finds the scalars with one
+// pass over the stages and recomputes each stage state where its
+// vector-Jacobian product needs it, instead of holding all of them: the same
+// arithmetic (bit for bit) with four fewer vectors live.
+template <class C>
+__device__ __forceinline__ void reverse_step_lean(const Problem<typename C::T>& P,
+                                                  const LaneParams<C>& L,
+                                                  const typename C::T (&g)[C::NPL],
+                                                  const typename C::T (&p)[C::NPL], bool aug,
+                                                  typename C::T (&lg)[C::NPL],
+                                                  typename C::T (&lp)[C::NPL]) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL;
+  const T h = P.h, h2 = T(0.5) * P.h, h6 = P.h / T(6), h3 = P.h / T(3);
+  StageScal<T> S[4];
+  T G[NPL], Pp[NPL];  // the stage state being visited
+  // pass 1: stage scalars; leaves stage 3 in (G, Pp)
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    G[k] = g[k];
+    Pp[k] = p[k];
+  }
+  S[0] = stage_scalars<C>(P, L, G, Pp);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const T cn = (s == 2) ? h : h2;
+    const T gn_c = -(cn * S[s].m), pn_c = cn * (S[s].q * S[s].m1 + P.w);  // as in rk4_step
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      const T gs = G[k], ps = Pp[k];
+      G[k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+      Pp[k] = __builtin_fma(pn_c, gs, p[k]);
+    }
+    S[s + 1] = stage_scalars<C>(P, L, G, Pp);
+  }
+  // pass 2: adjoint of the stages, last to first
+  T yg[NPL], yp[NPL], bg[NPL], bp[NPL];
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    yg[k] = lg[k];
+    yp[k] = lp[k];
+  }
+#pragma unroll
+  for (int s = 3; s >= 0; --s) {
+    const T wb = (s == 0 || s == 3) ? h6 : h3;
+    const T cn = (s == 2) ? h : h2;  // c_{s+1} h: offset of stage s+1 on K_s
+    if (s < 3) {
+      // stage state s from (g, p) through the recurrence
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        G[k] = g[k];
+        Pp[k] = p[k];
+      }
+#pragma unroll
+      for (int u = 0; u < s; ++u) {
+        const T cu = (u == 2) ? h : h2;
+        T gn_c = -(cu * S[u].m), pn_c = cu * (S[u].q * S[u].m1 + P.w);
+        // opaque copies: otherwise the compiler recognises the pass-1 values
+        // and keeps those stage states live instead of recomputing them
+        asm volatile("" : "+v"(gn_c), "+v"(pn_c));
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+          const T gs = G[k], ps = Pp[k];
+          G[k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+          Pp[k] = __builtin_fma(pn_c, gs, p[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      if (s == 3) {
+        bg[k] = wb * lg[k];
+        bp[k] = wb * lp[k];
+      } else {
+        bg[k] = wb * lg[k] + cn * bg[k];
+        bp[k] = wb * lp[k] + cn * bp[k];
+      }
+    }
+    vjp_stage<C>(P, L, G, Pp, S[s], aug ? wb : T(0), bg, bp);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      yg[k] += bg[k];
+      yp[k] += bp[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) {
+    lg[k] = yg[k];
+    lp[k] = yp[k];
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void reverse_step(const Problem<typename C::T>& P,
+                                             const LaneParams<C>& L,
+                                             const typename C::T (&g)[C::NPL],
+                                             const typename C::T (&p)[C::NPL], bool aug,
+                                             typename C::T (&lg)[C::NPL],
+                                             typename C::T (&lp)[C::NPL]) {
+  if constexpr (C::DR)
+    reverse_step_stored<C>(P, L, g, p, aug, lg, lp);
+  else
+    reverse_step_lean<C>(P, L, g, p, aug, lg, lp);
+}
+
 // lam += wk * grad(integrand)(y)   (trapezoid node term)
 template <class C>
 __device__ __forceinline__ void add_node_grad(const Problem<typename C::T>& P,
@@ -809,19 +934,28 @@ __device__ __forceinline__ void backward(const Problem<typename C::T>& P, const 
 #pragma unroll
   for (int k = 0; k < NPL; ++k) {
     if (P.formula == HJ_LAX) {
-      lg[k] = g[k] * L.ia2[k];
+      lg[k] = g[k] * L.ia2(k);
       lp[k] = T(0);
     } else {
       lg[k] = T(0);
-      lp[k] = L.a2[k] * p[k];
+      lp[k] = L.a2(k) * p[k];
     }
   }
+  // (ng, np_): the next state the sweep needs, loaded one step ahead so
+  // that the memory latency overlaps the arithmetic of the current step
+  T ng[NPL], np_[NPL];
+  load_state<T, NPL>(ck, stride, lane, nseg - 1, ng, np_);
   if (!aug) add_node_grad<C>(P, L, g, p, T(0.5) * P.h, lg, lp);
   for (int c = nseg - 1; c >= 0; --c) {
     const int k0 = c * K;
     const int k1 = (k0 + K < P.N) ? k0 + K : P.N;
-    load_state<T, NPL>(ck, stride, lane, c, g, p);
-    // recompute y_{k0+1} .. y_{k1-1} with the forward's own step function
+    // recompute y_{k0+1} .. y_{k1-1} from checkpoint c with the forward's
+    // own step function
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      g[k] = ng[k];
+      p[k] = np_[k];
+    }
     for (int j = k0 + 1; j < k1; ++j) {
       T gg[1][NPL], pp[1][NPL], dummy[1] = {T(0)};
 #pragma unroll
@@ -837,11 +971,24 @@ __device__ __forceinline__ void backward(const Problem<typename C::T>& P, const 
       }
       store_state<T, NPL>(seg, stride, lane, j - k0, g, p);
     }
+    // reverse sweep over the segment, starting from y_{k1-1} (in registers)
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      ng[k] = g[k];
+      np_[k] = p[k];
+    }
     for (int j = k1 - 1; j >= k0; --j) {
-      if (j == k0)
-        load_state<T, NPL>(ck, stride, lane, c, g, p);
-      else
-        load_state<T, NPL>(seg, stride, lane, j - k0, g, p);
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        g[k] = ng[k];
+        p[k] = np_[k];
+      }
+      if (j - 1 > k0)
+        load_state<T, NPL>(seg, stride, lane, j - 1 - k0, ng, np_);
+      else if (j - 1 == k0)
+        load_state<T, NPL>(ck, stride, lane, c, ng, np_);
+      else if (c > 0)
+        load_state<T, NPL>(ck, stride, lane, c - 1, ng, np_);  // next segment's start
       reverse_step<C>(P, L, g, p, aug, lg, lp);
       if (!aug) add_node_grad<C>(P, L, g, p, j == 0 ? T(0.5) * P.h : P.h, lg, lp);
     }

@@ -447,7 +447,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         gm = nanmax(gm, dabs(g[k]));
-        vt[0][k] = v[k] - alpha * g[k];
+        vt[0][k] = __builtin_fma(-alpha, g[k], v[k]);
       }
       smax = alpha * cmax<C>(gm);
       gg = csum<C>(dot2<NPL>(g, g));
@@ -456,8 +456,15 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
     best.n_fwd += 1;
     const bool acc = start || accept_step(A, ft[0], phi, alpha * gg);
     if (acc) {
+      if (!start) {
+        // the trial point again, from the same operands (bit-identical), so
+        // that it need not stay live across the solve; the empty asm keeps
+        // the compiler from reusing the first computation
+        T a = alpha;
+        asm volatile("" : "+v"(a));
 #pragma unroll
-      for (int k = 0; k < NPL; ++k) v[k] = vt[0][k];
+        for (int k = 0; k < NPL; ++k) v[k] = __builtin_fma(-a, g[k], v[k]);
+      }
       phi = ft[0];
       rho = rt[0];
     } else {

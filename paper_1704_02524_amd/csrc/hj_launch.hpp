@@ -123,6 +123,7 @@ constexpr int kNumDefaultShapes = 10;
 // Components per lane of the linear-drift (matrix-core) instances; the
 // padded dimension 4 * NPL is a multiple of 16, the MFMA block size.
 constexpr int kDriftNpl[] = {4, 8, 16};
+static_assert(4 * kDriftNpl[2] == HJ_MAX_N_DRIFT, "drift shapes cover HJ_MAX_N_DRIFT");
 
 }  // namespace hj
 

@@ -30,7 +30,7 @@ LPT_CHOICES = (1, 2, 4, 8, 16)
 
 def _key(wl) -> str:
     return (f"n{wl.n}_N{wl.nsteps}_G{wl.G}_B{wl.B}_dt{wl.dtype}_mode{wl.mode}"
-            f"_m{wl.m_kind}_q{wl.quad}")
+            f"_m{wl.m_kind}_q{wl.quad}_dr{int(wl.A is not None)}")
 
 
 def _load() -> Dict[str, dict]:
@@ -53,10 +53,12 @@ def candidates(wl):
     if wl.mode == W.GD_ADJ:
         ks = sorted({1, 4, 16, min(wl.ckpt_K, wl.nsteps)})
     out = []
-    for lpt in LPT_CHOICES:
-        if -(-wl.n // lpt) > 16:       # more than 16 components per lane
+    # a drift matrix runs on the matrix-core layout: 4 lanes per task only
+    lpts = (4,) if wl.A is not None else LPT_CHOICES
+    for lpt in lpts:
+        if wl.A is None and -(-wl.n // lpt) > 16:  # more than 16 components per lane
             continue
-        if lpt > 1 and wl.n <= lpt:    # lanes without a component
+        if wl.A is None and lpt > 1 and wl.n <= lpt:  # lanes without a component
             continue
         for K in ks:
             out.append(dict(lanes_per_task=lpt, **({} if K is None else {"ckpt_K": K})))
