@@ -63,6 +63,45 @@ def algorithmic_flops(wl, slot_fwd, slot_bwd):
         float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps, dr)
 
 
+def source_digest():
+    """Digest of the kernel sources and the C header (identifies the build
+    that counter measurements were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1704_02524_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "hj.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, launch):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/hbm_traffic.md: FETCH_SIZE and WRITE_SIZE, each scaled
+    by what the counter reads for a device copy of known size), when it was
+    taken on the current kernel sources with the same launch configuration;
+    otherwise None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    try:
+        with open(path) as f:
+            txt = f.read()
+        block = txt.split("```json", 1)[1].split("```", 1)[0]
+        entries = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    dig = source_digest()
+    for e in entries:
+        if e.get("workload") == workload and e.get("source_digest") == dig and \
+                e.get("launch") == launch:
+            return e["fetch_kib"] * 1024 * e["fetch_factor"] + \
+                e["write_kib"] * 1024 * e["write_factor"]
+    return None
+
+
 def _events(k):
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -126,33 +165,56 @@ def run_batched(wls, steps, warmup):
 
 
 def cpu_baseline(wls, budget_s=15.0):
-    """The FP64 reference, single-threaded, on points taken in turn from the
-    instances (a prefix of the points for one instance) with all their
-    guesses, until about budget_s seconds of work."""
+    """The FP64 reference, single-threaded, on (point, guess) slots taken in
+    order (points in turn from the instances), until about budget_s seconds
+    of work.  Rate: certified slots / G per second, i.e. point solves per
+    second when a point's G slots are solved in turn (a point counts as
+    certified once any of its slots is, so this does not overstate it)."""
     from oracle.oracle import Oracle, build
     build()
     oracles = [(Oracle.from_workload(w), Oracle.opts_from_workload(w)) for w in wls]
     t0 = time.perf_counter()
-    n_pts = n_cert = 0
-    nxt = [0] * len(wls)
+    n_slots = n_cert = 0
+    nxt = [0] * len(wls)  # next slot index (point * G + guess) per instance
     i = 0
-    while time.perf_counter() - t0 < budget_s and any(nxt[j] < wls[j].B for j in range(len(wls))):
+    while time.perf_counter() - t0 < budget_s and \
+            any(nxt[j] < wls[j].B * wls[j].G for j in range(len(wls))):
         j = i % len(wls)
-        i += 1
-        if nxt[j] >= wls[j].B:
+        w = wls[j]
+        if nxt[j] >= w.B * w.G:
+            i += 1
             continue
-        sub = wls[j].subset(nxt[j], nxt[j] + 1)
+        b, g = divmod(nxt[j], w.G)
         nxt[j] += 1
+        if nxt[j] % w.G == 0:
+            i += 1  # next instance after a whole point
+        sub = w.subset(b, b + 1)
         o, O = oracles[j]
-        r = o.solve(sub.x, sub.guesses, O, diag=False)
+        r = o.solve(sub.x, sub.guesses[:, g:g + 1], O, diag=False)
         n_cert += int(r["cert"][0] == 1)
-        n_pts += 1
+        n_slots += 1
     dt = time.perf_counter() - t0
-    what = (f"first {n_pts} points of the same workload" if len(wls) == 1 else
-            f"{n_pts} points taken in turn from the {len(wls)} instances")
-    return dict(value=n_cert / dt, unit="certified solves/s", cores=1, kind="oracle",
-                sample=f"{what} with all their guesses ({dt:.1f} s, {n_cert} certified), "
-                       f"FP64 reference, 1 thread")
+    G = wls[0].G
+    where = "the first points of the same workload" if len(wls) == 1 else \
+        f"points taken in turn from the {len(wls)} instances"
+    return dict(value=n_cert / G / dt, unit="certified solves/s", cores=1, kind="oracle",
+                sample=f"{n_slots} (point, guess) slots of {where} ({dt:.1f} s, {n_cert} "
+                       f"certified), FP64 reference, 1 thread; rate = certified slots / "
+                       f"{G} guesses per second")
+
+
+def copy_probe(nbytes):
+    """A device-to-device copy of nbytes, so that a counter run over this
+    process also sees a kernel of known traffic (nbytes read, nbytes
+    written) to scale FETCH_SIZE / WRITE_SIZE by."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: {nbytes} bytes device to device")
+    del a, b
 
 
 def describe(wl):
@@ -198,10 +260,13 @@ def main():
     ap.add_argument("--points", type=int, default=None,
                     help="query points (per instance for the batched workload)")
     ap.add_argument("--cd-points", type=int, default=None,
-                    help="points of the central-FD comparison run (default: all)")
+                    help="points of the central-FD comparison run (the n=10 workload runs it "
+                         "on all points by default; other workloads only with this option)")
     ap.add_argument("--no-cd", action="store_true", help="skip the central-FD comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="bytes of a device copy run first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
@@ -214,6 +279,8 @@ def main():
     from paper_1704_02524_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
     wls = build_workloads(args.workload, args.points)
     wl = wls[0]
     batched = len(wls) > 1
@@ -269,12 +336,17 @@ def main():
         "config": config,
         "roofline": {
             "bound": bound, "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(args.workload, cfg),
             "kernel": kernel, "launch": cfg, "kernel_ms": float(np.mean(kern)),
             "algorithmic_flops_per_launch": flops,
         },
     }
-    if not batched and wl.mode == W.GD_ADJ and not args.no_cd:
+    # the central-FD comparison: the whole n=10 workload by default; for the
+    # other workloads only on request (--cd-points), since coordinate descent
+    # costs 3n solves per sweep
+    want_cd = args.workload == "hopf_n10" or args.cd_points is not None
+    if not batched and wl.mode == W.GD_ADJ and want_cd and not args.no_cd:
         wcd = wl.with_(mode=W.CD_FD)
         if args.cd_points:
             wcd = wcd.subset(0, min(args.cd_points, wl.B))
