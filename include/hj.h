@@ -136,7 +136,8 @@ typedef struct {
     void   *ev_end;       /* optional hipEvent_t recorded just after it    */
     int32_t schedule;     /* HJ_SCHED_*: how (point, guess) tasks reach the
                              lanes                                          */
-    int32_t reserved2;
+    int32_t max_groups;   /* persistent schedule: at most this many lane
+                             groups (0: as many as the device holds)       */
 } hj_opts;
 
 enum {

@@ -321,9 +321,11 @@ int64_t dispatch_resident(const Shape& s, int mk, int mode) {
 
 // Lane groups of a persistent launch (0: one group per task).
 template <typename T>
-int64_t schedule_groups(const Shape& s, int mk, int mode, int sched, int64_t ntask) {
+int64_t schedule_groups(const Shape& s, int mk, int mode, int sched, int64_t ntask,
+                        int max_groups) {
   if (sched == HJ_SCHED_STATIC) return 0;
-  const int64_t res = dispatch_resident<T>(s, mk, mode);
+  int64_t res = dispatch_resident<T>(s, mk, mode);
+  if (max_groups > 0) res = std::min<int64_t>(res, max_groups);
   if (res <= 0) return 0;
   if (sched == HJ_SCHED_PERSISTENT) return std::min(res, ntask);
   // automatic: persistent once the tasks fill the device twice over
@@ -373,7 +375,8 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
   const int64_t ntask = B * (int64_t)gs->G;
-  const int64_t groups = schedule_groups<T>(s, kernel_mk(H), o->mode, o->schedule, ntask);
+  const int64_t groups =
+      schedule_groups<T>(s, kernel_mk(H), o->mode, o->schedule, ntask, o->max_groups);
   // a persistent launch holds checkpoints for its resident lanes only
   const size_t ck_lanes = groups > 0 ? align_up((size_t)groups * s.lpt, 256) : 0;
   WsLayout WL = layout(s, n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes);
@@ -522,6 +525,7 @@ int check_opts(const hj_opts* o) {
   if (o->lanes_per_task < 0) return fail(HJ_EINVAL, "lanes_per_task must be >= 0");
   if (o->schedule < HJ_SCHED_AUTO || o->schedule > HJ_SCHED_PERSISTENT)
     return fail(HJ_EINVAL, "bad schedule");
+  if (o->max_groups < 0) return fail(HJ_EINVAL, "max_groups must be >= 0");
   return HJ_OK;
 }
 
@@ -586,7 +590,8 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
       g.points += inst[i].B;
       g.max_steps = std::max(g.max_steps, inst[i].nsteps);
     }
-    const int64_t res = dispatch_resident<T>(g.s, g.mk, HJ_GD_ADJ);
+    int64_t res = dispatch_resident<T>(g.s, g.mk, HJ_GD_ADJ);
+    if (o->max_groups > 0) res = std::min<int64_t>(res > 0 ? res : g.tasks, o->max_groups);
     g.groups = std::max<int64_t>(1, std::min(res > 0 ? res : g.tasks, g.tasks));
   }
   // memory layout

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
   const int sub = C::sub_of(threadIdx.x);
   int64_t task = C::task_of(lane);
   // matrix-core kernels keep lanes without a task as idle wave members
-  bool live = task < A.ntask;
+  int live = task < A.ntask ? 1 : 0;
   if constexpr (!C::DR) {
     if (!live) return;
   }
@@ -317,16 +317,20 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
     stage_drift<C>(A.P.aop, s_aop);
     tc.L.aop = s_aop;
   }
-  tc.bind(A, live ? task : 0, sub);
+  tc.bind(A, live != 0 ? task : 0, sub);
   const int n = A.P.n;
   T v[NPL];
   load_row<C>(tc.g0, n, sub, v);
   SlotBest best;
   best.reset();
-  int att = 0, it = 0, j = 0;
-  bool start = true;
+  // it < 0 marks the first pass of an attempt (its start point is evaluated).
+  // The attempt start is kept in this many-valued counter rather than in a
+  // loop-carried flag: the compiler's lowering of such a flag in this loop
+  // (a per-lane mask) has lost the restart of a new task.
+  int att = 0, it = -1, j = 0;
   T alpha = A.alpha0, phi = T(0), rho = T(0), smax = T(0);
   while (true) {
+    const bool start = it < 0;
     // pair: the two central-difference points (or the start point)
     T va[2][NPL], fp[2], rp[2];
 #pragma unroll
@@ -348,7 +352,6 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
       best.n_fwd += 1;
       phi = fp[0];
       rho = rp[0];
-      start = false;
       it = 0;
       j = 0;
       smax = T(0);
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
         smax = T(0);
       }
     }
-    const bool ending = live && status >= 0;
+    const bool ending = live != 0 && status >= 0;
     double phi64, rho64;
     attempt_values<C, false>(A, tc, sub, v, phi, rho, status, ending, phi64, rho64);
     if (ending) {
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
         att = 0;
         if (task < 0) {
           if constexpr (!C::DR) break;
-          live = false;
+          live = 0;
         } else {
           tc.bind(A, task, sub);
           best.reset();
@@ -394,10 +397,10 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
         ++att;
       }
       load_row<C>(tc.g0 + (int64_t)att * n, n, sub, v);
-      start = true;
+      it = -1;
     }
     if constexpr (C::DR) {
-      if (!wave_if<C>(live)) break;
+      if (!wave_if<C>(live != 0)) break;
     }
   }
 }
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
   const int sub = C::sub_of(threadIdx.x);
   int64_t task = C::task_of(lane);
   // matrix-core kernels keep lanes without a task as idle wave members
-  bool live = task < A.ntask;
+  int live = task < A.ntask ? 1 : 0;
   if constexpr (!C::DR) {
     if (!live) return;
   }
@@ -425,17 +428,18 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
     stage_drift<C>(A.P.aop, s_aop);
     tc.L.aop = s_aop;
   }
-  tc.bind(A, live ? task : 0, sub);
+  tc.bind(A, live != 0 ? task : 0, sub);
   T v[NPL], g[NPL];
   load_row<C>(tc.g0, tc.P(A).n, sub, v);
 #pragma unroll
   for (int k = 0; k < NPL; ++k) g[k] = T(0);
   SlotBest best;
   best.reset();
-  int att = 0, it = 0;
-  bool start = true;
+  // it < 0 marks the first pass of an attempt (see k_solve_cd)
+  int att = 0, it = -1;
   T alpha = A.alpha0, phi = T(0), rho = T(0);
   while (true) {
+    const bool start = it < 0;
     const Problem<T>& P = tc.P(A);
     // trial point
     T vt[1][NPL], ft[1], rt[1], smax = T(0), gg = T(0);
@@ -482,7 +486,6 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
     }
     int status = -1;
     if (start) {
-      start = false;
       it = 0;
       alpha = A.alpha0;
       if (!isfinite(phi))
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
       ++it;
       status = stop_status<C>(A, v, phi, smax, alpha, it);
     }
-    const bool ending = live && status >= 0;
+    const bool ending = live != 0 && status >= 0;
     double phi64, rho64;
     attempt_values<C, MULTI>(A, tc, sub, v, phi, rho, status, ending, phi64, rho64);
     if (ending) {
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
         att = 0;
         if (task < 0) {
           if constexpr (!C::DR) break;
-          live = false;
+          live = 0;
         } else {
           tc.bind(A, task, sub);
           best.reset();
@@ -512,10 +515,10 @@ __global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
         ++att;
       }
       load_row<C>(tc.g0 + (int64_t)att * tc.P(A).n, tc.P(A).n, sub, v);
-      start = true;
+      it = -1;
     }
     if constexpr (C::DR) {
-      if (!wave_if<C>(live)) break;
+      if (!wave_if<C>(live != 0)) break;
     }
   }
 }

@@ -47,7 +47,7 @@ class Opts(C.Structure):
                 ("armijo_c", C.c_double),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("schedule", C.c_int32),
-                ("reserved2", C.c_int32)]
+                ("max_groups", C.c_int32)]
 
 SCHED_AUTO, SCHED_STATIC, SCHED_PERSISTENT = 0, 1, 2
 

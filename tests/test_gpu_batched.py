@@ -100,3 +100,41 @@ def test_batched_fp32(hj):
         err = np.abs(got["u"][:2][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
         assert err.max(initial=0.0) <= 1e-4, (w.name, err)
     plan.free()
+
+
+@pytest.mark.parametrize("dtype,mode", [(W.F64, W.GD_ADJ), (W.F32, W.GD_ADJ),
+                                        (W.F64, W.CD_FD)])
+@pytest.mark.parametrize("lpt", [1, 2])
+def test_persistent_many_tasks_per_group_equals_static(hj, dtype, mode, lpt):
+    """A persistent launch capped at 64 lane groups (each group runs about 24
+    tasks in turn, with restarts) gives every slot the result a one-task
+    launch gives it, bit for bit: nothing of a finished task carries over."""
+    wl = W.c1_hopf_n10(B=96)
+    if dtype == W.F32:
+        wl = W._as_dtype(wl.with_(eps_step=1e-6, cert_tol=1e-4))
+    wl = wl.with_(max_iter=60, mode=mode)
+    if mode == W.CD_FD:
+        wl = wl.with_(guesses=wl.guesses[:, :4].copy(), max_iter=20)
+    x, g = hj.device_inputs(wl)
+    a = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_STATIC))
+    b = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_PERSISTENT,
+                       max_groups=64))
+    assert (a["slot_attempts"] > 1).any()  # restarts happen
+    for k in a:
+        np.testing.assert_array_equal(np.nan_to_num(a[k]), np.nan_to_num(b[k]), err_msg=k)
+
+
+def test_batched_persistent_equals_single(hj):
+    """Batched instances in a persistent launch of 32 lane groups per shape
+    agree slot by slot with single-instance static solves."""
+    wls = _batch(n_inst=4, max_points=24)
+    plan = hj.BatchPlan(wls, max_groups=32)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    for w, out in zip(wls, outs):
+        ref = _host(hj.solve(w, *hj.device_inputs(w), schedule=hj.SCHED_STATIC))
+        got = _host(out)
+        for k in ("slot_fwd", "slot_iters", "slot_attempts", "cert"):
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+        np.testing.assert_allclose(got["u"], ref["u"], rtol=1e-13, atol=1e-13)
+    plan.free()
