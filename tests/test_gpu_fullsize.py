@@ -1,0 +1,80 @@
+"""Full-size launches of the n=32 drift, n=100 FP32 and batched workloads,
+in the configurations bench.py times, with sampled points checked against
+the FP64 reference one by one (the reference solves a point in about a
+second).  FP64: u to 1e-9 max(1, |u|) and equal certificate flags; FP32:
+u to 1e-4 max(1, |u|) where both certify."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle, build as build_oracle
+from paper_1704_02524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+build_oracle()
+
+
+@pytest.fixture(scope="module")
+def hj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_02524_amd import hj as _hj
+    return _hj
+
+
+def _check_point(wl, b, got_u, got_cert, got_arg, tol_u, tol_arg):
+    sub = wl.subset(b, b + 1)
+    ref = Oracle.from_workload(sub).solve(sub.x, sub.guesses, Oracle.opts_from_workload(sub))
+    if wl.dtype == W.F64:
+        assert got_cert == ref["cert"][0], (wl.name, b)
+    if got_cert >= 0 and ref["cert"][0] >= 0 and (wl.dtype == W.F64 or got_cert == ref["cert"][0]):
+        err = abs(got_u - ref["u"][0]) / max(1.0, abs(ref["u"][0]))
+        assert err <= tol_u, (wl.name, b, err)
+        if got_cert == 1 and ref["cert"][0] == 1 and tol_arg is not None:
+            aerr = np.abs(got_arg - ref["argopt"][0]).max() / max(1.0, np.abs(ref["argopt"][0]).max())
+            assert aerr <= tol_arg, (wl.name, b, aerr)
+
+
+def test_drift_n32_full_size_sampled(hj):
+    """65536 points x 8 guesses, 256 steps, A on the matrix cores (the
+    checkpoint interval does not change results: bit-identical gradients)."""
+    wl = W.c3_drift_n32()
+    res = hj.solve(wl, *hj.device_inputs(wl), ckpt_K=1)
+    torch.cuda.synchronize()
+    u, cert, arg = (res[k].cpu().numpy() for k in ("u", "cert", "argopt"))
+    assert (cert == 1).mean() > 0.999
+    for b in [0, 31337, 65535]:
+        _check_point(wl, b, u[b], cert[b], arg[b], 1e-9, 1e-6)
+
+
+def test_lax_n100_fp32_full_size_sampled(hj):
+    """262144 points x 4 guesses, FP32 descent with the FP64 certificate, in
+    a persistent launch (more tasks than resident lane groups)."""
+    wl = W.c4_lax_n100()
+    res = hj.solve(wl, *hj.device_inputs(wl), lanes_per_task=8, ckpt_K=1)
+    torch.cuda.synchronize()
+    u, cert, arg = (res[k].cpu().numpy() for k in ("u", "cert", "argopt"))
+    assert (cert == 1).mean() > 0.999
+    for b in [0, 123457, 262143]:
+        _check_point(wl, b, u[b], cert[b], arg[b], 1e-4, None)
+
+
+@pytest.mark.parametrize("dtype", [W.F64, W.F32])
+def test_batched_full_size_sampled(hj, dtype):
+    """All 64 instances in one captured plan; two points of each of eight
+    instances (different n, t, N) against the reference."""
+    wls = W.c2_batched(dtype=dtype)
+    plan = hj.BatchPlan(wls)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    tot = sum(w.B for w in wls)
+    ncert = sum(int((o["cert"] == 1).sum().item()) for o in outs)
+    assert ncert / tot > (0.999 if dtype == W.F64 else 0.98)
+    tol = 1e-9 if dtype == W.F64 else 1e-4
+    for i in range(0, 64, 8):
+        w, o = wls[i], outs[i]
+        u, cert, arg = (o[k].cpu().numpy() for k in ("u", "cert", "argopt"))
+        for b in [0, w.B - 1]:
+            _check_point(w, b, u[b], cert[b], arg[b], tol, 1e-6 if dtype == W.F64 else None)
+    plan.free()
