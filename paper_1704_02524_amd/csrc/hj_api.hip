@@ -44,8 +44,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // The lane shape for n: with drift, the smallest matrix-core shape covering
 // n (4 lanes per task); otherwise with lpt == 0 the first default shape
-// covering n, else the smallest compiled shape with that many lanes per task.
-bool pick_shape(int n, int lpt, bool drift, Shape& s) {
+// covering n (FP32 with 64 < n <= 112: 16 lanes of 7 components), else the
+// smallest compiled shape with that many lanes per task.
+bool pick_shape(int n, int lpt, bool drift, bool f32, Shape& s) {
   if (drift) {
     if (lpt != 0 && lpt != 4) return false;
     for (int npl : hj::kDriftNpl)
@@ -56,6 +57,10 @@ bool pick_shape(int n, int lpt, bool drift, Shape& s) {
     return false;
   }
   if (lpt == 0) {
+    if (f32 && n > 64 && n <= hj::kF32Wide.npad()) {
+      s = hj::kF32Wide;
+      return true;
+    }
     for (int i = 0; i < hj::kNumDefaultShapes; ++i)
       if (n <= hj::kShapes[i].npad()) {
         s = hj::kShapes[i];
@@ -353,9 +358,9 @@ hipError_t dispatch_eval(const Shape& s, int mk, const hj::EvalArgs<T>& A, hipSt
 }
 
 // The lane shape of a problem, or an error naming what is not compiled.
-int shape_for(const hj_h_params* H, int n, int lpt, Shape& s) {
+int shape_for(const hj_h_params* H, int n, int lpt, bool f32, Shape& s) {
   const bool drift = H->A != nullptr;
-  if (pick_shape(n, lpt, drift, s)) return HJ_OK;
+  if (pick_shape(n, lpt, drift, f32, s)) return HJ_OK;
   if (drift)
     return fail(HJ_EUNSUPPORTED, "the drift kernels take n <= " +
                                      std::to_string(HJ_MAX_N_DRIFT) +
@@ -370,7 +375,7 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
             double t, int nsteps, const hj_guesses* gs, const hj_opts* o, double* out_u,
             void* out_argopt, int32_t* out_cert, const hj_slot_diag* diag) {
   Shape s{};
-  int rc = shape_for(H, n, o->lanes_per_task, s);
+  int rc = shape_for(H, n, o->lanes_per_task, sizeof(T) == 4, s);
   if (rc) return rc;
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
@@ -454,7 +459,7 @@ int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B,
            double t, int nsteps, const void* v, int G, const hj_opts* o, double* out_phi,
            void* out_yN, double* out_rho, void* out_gv, void* out_gx) {
   Shape s{};
-  int rc = shape_for(H, n, o->lanes_per_task, s);
+  int rc = shape_for(H, n, o->lanes_per_task, sizeof(T) == 4, s);
   if (rc) return rc;
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
@@ -569,7 +574,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
   std::vector<LaunchGroup> lg;
   for (int i = 0; i < n_inst; ++i) {
     Shape s{};
-    if (!pick_shape(inst[i].n, o->lanes_per_task, false, s))
+    if (!pick_shape(inst[i].n, o->lanes_per_task, false, sizeof(T) == 4, s))
       return fail(HJ_EUNSUPPORTED, "no kernel shape for instance " + std::to_string(i));
     const int mk = kernel_mk(&inst[i].H);
     auto it = std::find_if(lg.begin(), lg.end(), [&](const LaunchGroup& g) {
@@ -798,7 +803,7 @@ size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const 
   size_t need = 0;
   for (int drift = 0; drift < 2; ++drift) {
     Shape s{};
-    if (!pick_shape(n, o.lanes_per_task, drift != 0, s)) continue;
+    if (!pick_shape(n, o.lanes_per_task, drift != 0, o.dtype == HJ_F32, s)) continue;
     WsLayout a = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, false, true);
     WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
     need = std::max(need, std::max(a.total, b.total));

@@ -213,6 +213,13 @@ template <typename T_, int NPL_, int LPT_, int MK_, bool DR_ = false> struct Cfg
   }
   // elements of the MFMA operand table of A and A^T: [2][NPL/4][NPL][64]
   static constexpr int kDriftTable = DR ? 2 * (NPL / 4) * NPL * 64 : 0;
+  // waves per SIMD the descent kernel is compiled for (register budget 512 /
+  // kWaves per lane).  FP32 with at most 5 components per lane, or 16 lanes
+  // per task, fits two waves with a spill of at most a few hundred bytes
+  // that stays out of the RK4 loops, and the second wave's latency hiding
+  // pays (measured); FP64 and wider FP32 shapes lose more to spills at two
+  // waves than they gain.
+  static constexpr int kWaves = (!DR && sizeof(T) == 4 && (LPT == 16 || NPL <= 5)) ? 2 : 1;
 };
 
 // Sum / max over the lanes of a task group.

@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
 // gradient descent with the exact discrete gradient (adjoint + checkpoints)
 // ---------------------------------------------------------------------------
 template <class C, bool MULTI>
-__global__ __launch_bounds__(256) void k_solve_gd(SolveArgs<typename C::T> A) {
+__global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
   constexpr int NPL = C::NPL;
   static_assert(!(MULTI && C::DR), "batched instances carry no drift");

@@ -120,6 +120,9 @@ constexpr Shape kShapes[] = {
     {2, 2}, {8, 1}, {2, 4}, {10, 1}, {8, 2}, {4, 8}, {7, 16},
 };
 constexpr int kNumDefaultShapes = 10;
+// FP32 default for 64 < n <= 112: 16 lanes of 7 components, whose descent
+// kernel runs two waves per SIMD (the wider FP32 shapes run one)
+constexpr Shape kF32Wide = {7, 16};
 // Components per lane of the linear-drift (matrix-core) instances; the
 // padded dimension 4 * NPL is a multiple of 16, the MFMA block size.
 constexpr int kDriftNpl[] = {4, 8, 16};

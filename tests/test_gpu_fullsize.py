@@ -50,9 +50,10 @@ def test_drift_n32_full_size_sampled(hj):
 
 def test_lax_n100_fp32_full_size_sampled(hj):
     """262144 points x 4 guesses, FP32 descent with the FP64 certificate, in
-    a persistent launch (more tasks than resident lane groups)."""
+    a persistent launch (more tasks than resident lane groups), on 16 lanes
+    of 7 components per task at two waves per SIMD."""
     wl = W.c4_lax_n100()
-    res = hj.solve(wl, *hj.device_inputs(wl), lanes_per_task=8, ckpt_K=1)
+    res = hj.solve(wl, *hj.device_inputs(wl), lanes_per_task=16, ckpt_K=1)
     torch.cuda.synchronize()
     u, cert, arg = (res[k].cpu().numpy() for k in ("u", "cert", "argopt"))
     assert (cert == 1).mean() > 0.999
