@@ -542,6 +542,8 @@ int check_opts(const hj_opts* o) {
 struct hj_batch_plan_s {
   void* mem = nullptr;
   hipStream_t cap = nullptr;
+  std::vector<hipStream_t> branch;  // capture streams of the launch groups after the first
+  std::vector<hipEvent_t> ev;       // fork and join events of the capture
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t tasks = 0, groups = 0;
@@ -549,6 +551,8 @@ struct hj_batch_plan_s {
   ~hj_batch_plan_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipStream_t b : branch) (void)hipStreamDestroy(b);
     if (cap) (void)hipStreamDestroy(cap);
     if (mem) (void)hipFree(mem);
   }
@@ -715,19 +719,40 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     A.n_inst = (int)g.inst.size();
     args.push_back(A);
   }
-  // capture the launch sequence into a graph
+  // capture the launch groups into a graph as parallel branches (fork from
+  // the capture stream, join back into it): the groups share no memory, and
+  // a group's persistent launch ends with a tail of long tasks on few CUs
+  // that the next group's work can fill.  Every stream has the default
+  // priority.
   HJ_HIP(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking));
+  for (size_t gi = 1; gi < lg.size(); ++gi) {
+    hipStream_t b = nullptr;
+    HJ_HIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    plan->branch.push_back(b);
+  }
+  for (size_t i = 0; i < lg.size(); ++i) {  // fork, then one join per branch
+    hipEvent_t e = nullptr;
+    HJ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    plan->ev.push_back(e);
+  }
   HJ_HIP(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
-  hipError_t err = hipSuccess;
+  hipError_t err = hipEventRecord(plan->ev[0], plan->cap);
+  for (size_t gi = 1; gi < lg.size() && err == hipSuccess; ++gi)
+    err = hipStreamWaitEvent(plan->branch[gi - 1], plan->ev[0], 0);
   for (size_t gi = 0; gi < lg.size() && err == hipSuccess; ++gi) {
     const LaunchGroup& g = lg[gi];
     const hj::SolveArgs<T>& A = args[gi];
-    err = dispatch_solve<T>(g.s, g.mk, A, HJ_GD_ADJ, g.groups, plan->cap);
+    hipStream_t st = gi == 0 ? plan->cap : plan->branch[gi - 1];
+    err = dispatch_solve<T>(g.s, g.mk, A, HJ_GD_ADJ, g.groups, st);
     if (err == hipSuccess)
       err = hj::launch_select_batched<T>(A.inst, A.n_inst, g.points, A.P.n, o->formula,
-                                         A.out.phi, A.out.cert, A.out.v, plan->cap);
+                                         A.out.phi, A.out.cert, A.out.v, st);
     if (err == hipSuccess)
-      err = hj::launch_scatter_diag<T>(A.inst, A.n_inst, g.tasks, A.P.n, A.out, plan->cap);
+      err = hj::launch_scatter_diag<T>(A.inst, A.n_inst, g.tasks, A.P.n, A.out, st);
+  }
+  for (size_t gi = 1; gi < lg.size() && err == hipSuccess; ++gi) {
+    err = hipEventRecord(plan->ev[gi], plan->branch[gi - 1]);
+    if (err == hipSuccess) err = hipStreamWaitEvent(plan->cap, plan->ev[gi], 0);
   }
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(plan->cap, &graph);
