@@ -1,7 +1,7 @@
-"""Full-size launches of the n=32 drift, n=100 FP32 and batched workloads,
-in the configurations bench.py times, with sampled points checked against
-the FP64 reference one by one (the reference solves a point in about a
-second).  FP64: u to 1e-9 max(1, |u|) and equal certificate flags; FP32:
+"""Full-size launches of the n=10 Hopf, n=32 drift, n=100 FP32 and batched
+workloads, in the configurations bench.py times, with sampled points checked
+against the FP64 reference one by one (the reference solves a point in about
+a second).  FP64: u to 1e-9 max(1, |u|) and equal certificate flags; FP32:
 u to 1e-4 max(1, |u|) where both certify."""
 import numpy as np
 import pytest
@@ -45,6 +45,18 @@ def test_drift_n32_full_size_sampled(hj):
     u, cert, arg = (res[k].cpu().numpy() for k in ("u", "cert", "argopt"))
     assert (cert == 1).mean() > 0.999
     for b in [0, 31337, 65535]:
+        _check_point(wl, b, u[b], cert[b], arg[b], 1e-9, 1e-6)
+
+
+def test_hopf_n10_full_size_sampled(hj):
+    """4096 points x 16 guesses on one lane per task with checkpoints every
+    16 steps, the launch the headline benchmark times."""
+    wl = W.c1_hopf_n10(B=4096)
+    res = hj.solve(wl, *hj.device_inputs(wl), lanes_per_task=1, ckpt_K=16)
+    torch.cuda.synchronize()
+    u, cert, arg = (res[k].cpu().numpy() for k in ("u", "cert", "argopt"))
+    assert (cert == 1).mean() > 0.999
+    for b in [0, 1111, 2048, 4095] + list(np.where(cert != 1)[0][:2]):
         _check_point(wl, b, u[b], cert[b], arg[b], 1e-9, 1e-6)
 
 
