@@ -189,12 +189,17 @@ template <int NPL, typename T> __device__ __forceinline__ T tree_sum(const T (&a
 // MK: speed profile (HJ_M_TANH, or HJ_M_RAT which also serves HJ_M_CONST
 // with kappa = 0: c = 1 and c' = c'' = 0 exactly); DR: linear drift
 // <A x, p> in H, on the matrix-core layout (LPT = 4, NPL a multiple of 4).
-template <typename T_, int NPL_, int LPT_, int MK_, bool DR_ = false> struct Cfg {
+template <typename T_, int NPL_, int LPT_, int MK_, bool DR_ = false,
+          bool DL_ = DR_ && sizeof(T_) == 8>
+struct Cfg {
   using T = T_;
   static constexpr int NPL = NPL_;
   static constexpr int LPT = LPT_;
   static constexpr int MK = MK_;
   static constexpr bool DR = DR_;
+  // weights d read from LDS at every use (see LaneParams::dk)
+  static constexpr bool DL = DL_;
+  static_assert(!DL || DR, "LDS weights belong to the matrix-core layout");
   static_assert(!DR || (LPT == 4 && NPL % 4 == 0), "drift layout: 4 lanes, NPL % 4 == 0");
   // vector component held in slot k of lane `sub`
   static __device__ __forceinline__ int comp(int sub, int k) {
@@ -274,6 +279,26 @@ template <class C> struct LaneParams {
     a2p = P.a2;
     ia2p = P.ia2;
     aop = P.aop;
+  }
+  // The FP64 matrix-core kernels read d from LDS (element 4k + sub is the
+  // lane's slot k) at every use, through a pointer the compiler cannot see
+  // through: held in registers for the whole kernel, as it would hoist
+  // them, the per-lane weights are what spills first on that layout, and
+  // the reloads then wait behind the checkpoint stores (5% of the n = 32
+  // solve).  In FP32 kernels, and in their FP64 certificate solve, they fit
+  // and the reads would only cost (measured).
+  static constexpr bool kDlds = C::DL;
+  typedef const __attribute__((address_space(3))) T* lds_ptr;
+  lds_ptr dl;
+  __device__ __forceinline__ void set_dl(const T* p) { dl = (lds_ptr)(p + sub); }
+  __device__ __forceinline__ T dk(int k) const {
+    if constexpr (kDlds) {
+      lds_ptr q = dl;
+      asm volatile("" : "+v"(q));
+      return q[4 * k];
+    } else {
+      return d[k];
+    }
   }
   __device__ __forceinline__ T a2(int k) const { return a2p[C::comp(sub, k)]; }
   __device__ __forceinline__ T ia2(int k) const { return ia2p[C::comp(sub, k)]; }
@@ -401,7 +426,7 @@ __device__ __forceinline__ void reduce_rq(const typename C::T (&G)[NT][C::NPL],
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
 #pragma unroll
-    for (int k = 0; k < C::NPL; ++k) dp[t][k] = L.d[k] * Pp[t][k];
+    for (int k = 0; k < C::NPL; ++k) dp[t][k] = L.dk(k) * Pp[t][k];
     r[t] = dot2<C::NPL>(G[t], G[t]);
     q[t] = dot2<C::NPL>(dp[t], Pp[t]);
   }
@@ -644,7 +669,7 @@ __device__ __forceinline__ StageScal<typename C::T> stage_scalars(
   StageScal<T> S;
   T dp[C::NPL];
 #pragma unroll
-  for (int k = 0; k < C::NPL; ++k) dp[k] = L.d[k] * Pp[k];
+  for (int k = 0; k < C::NPL; ++k) dp[k] = L.dk(k) * Pp[k];
   S.r = csum<C>(dot2<C::NPL>(G, G));
   S.q = csum<C>(dot2<C::NPL>(dp, Pp));
   speed<C, true>(P, S.r, S.m, S.m1, S.m2);
@@ -682,7 +707,7 @@ __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const
   constexpr int NPL = C::NPL;
   T dp[NPL];
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) dp[k] = L.d[k] * Pp[k];
+  for (int k = 0; k < NPL; ++k) dp[k] = L.dk(k) * Pp[k];
   const T s1 = csum<C>(dot2<NPL>(dp, kg));
   const T s2 = csum<C>(dot2<NPL>(G, kp));
   T cg = T(0), cp = T(0);
@@ -696,7 +721,7 @@ __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       const T og = __builtin_fma(al, kp[k], __builtin_fma(ag, G[k], -ATk[k]));
-      const T op = __builtin_fma(ap, dp[k], __builtin_fma(-S.m, L.d[k] * kg[k], Ak[k]));
+      const T op = __builtin_fma(ap, dp[k], __builtin_fma(-S.m, L.dk(k) * kg[k], Ak[k]));
       kg[k] = og;
       kp[k] = op;
     }
@@ -704,7 +729,7 @@ __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       const T og = __builtin_fma(al, kp[k], ag * G[k]);
-      const T op = __builtin_fma(ap, dp[k], -S.m * (L.d[k] * kg[k]));
+      const T op = __builtin_fma(ap, dp[k], -S.m * (L.dk(k) * kg[k]));
       kg[k] = og;
       kp[k] = op;
     }
@@ -743,7 +768,7 @@ __device__ __forceinline__ void reverse_step_stored(const Problem<typename C::T>
       for (int k = 0; k < NPL; ++k) {
         const T gs = s ? YG[s - 1][k] : g[k];
         const T ps = s ? YP[s - 1][k] : p[k];
-        YG[s][k] = __builtin_fma(gn_c, L.d[k] * ps, __builtin_fma(-cn, AG[k], g[k]));
+        YG[s][k] = __builtin_fma(gn_c, L.dk(k) * ps, __builtin_fma(-cn, AG[k], g[k]));
         YP[s][k] = __builtin_fma(pn_c, gs, __builtin_fma(cn, ATP[k], p[k]));
       }
     } else {
@@ -751,7 +776,7 @@ __device__ __forceinline__ void reverse_step_stored(const Problem<typename C::T>
       for (int k = 0; k < NPL; ++k) {
         const T gs = s ? YG[s - 1][k] : g[k];
         const T ps = s ? YP[s - 1][k] : p[k];
-        YG[s][k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+        YG[s][k] = __builtin_fma(gn_c, L.dk(k) * ps, g[k]);
         YP[s][k] = __builtin_fma(pn_c, gs, p[k]);
       }
     }
@@ -828,7 +853,7 @@ __device__ __forceinline__ void reverse_step_lean(const Problem<typename C::T>& 
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       const T gs = G[k], ps = Pp[k];
-      G[k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+      G[k] = __builtin_fma(gn_c, L.dk(k) * ps, g[k]);
       Pp[k] = __builtin_fma(pn_c, gs, p[k]);
     }
     S[s + 1] = stage_scalars<C>(P, L, G, Pp);
@@ -861,7 +886,7 @@ __device__ __forceinline__ void reverse_step_lean(const Problem<typename C::T>& 
 #pragma unroll
         for (int k = 0; k < NPL; ++k) {
           const T gs = G[k], ps = Pp[k];
-          G[k] = __builtin_fma(gn_c, L.d[k] * ps, g[k]);
+          G[k] = __builtin_fma(gn_c, L.dk(k) * ps, g[k]);
           Pp[k] = __builtin_fma(pn_c, gs, p[k]);
         }
       }
@@ -918,7 +943,7 @@ __device__ __forceinline__ void add_node_grad(const Problem<typename C::T>& P,
 #pragma unroll
   for (int k = 0; k < C::NPL; ++k) {
     lg[k] += wk * cg * g[k];
-    lp[k] += wk * cp * L.d[k] * p[k];
+    lp[k] += wk * cp * L.dk(k) * p[k];
   }
 }
 

@@ -33,11 +33,14 @@ __device__ __forceinline__ void store_row(typename C::T* base, int n, int sub,
   }
 }
 
-// Copy the drift operand table into the workgroup's LDS (every thread of the
-// block takes part; the matrix-core kernels never leave before this point).
+// Copy the drift operand table and the padded weights d into the
+// workgroup's LDS (every thread of the block takes part; the matrix-core
+// kernels never leave before this point).
 template <class C>
-__device__ __forceinline__ void stage_drift(const typename C::T* src, typename C::T* dst) {
-  for (int i = threadIdx.x; i < C::kDriftTable; i += blockDim.x) dst[i] = src[i];
+__device__ __forceinline__ void stage_drift(const typename C::T* table, const typename C::T* d,
+                                            typename C::T* dst) {
+  for (int i = threadIdx.x; i < C::kDriftTable; i += blockDim.x) dst[i] = table[i];
+  for (int i = threadIdx.x; i < 4 * C::NPL; i += blockDim.x) dst[C::kDriftTable + i] = d[i];
   __syncthreads();
 }
 
@@ -48,7 +51,7 @@ template <class C>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C::T> A) {
   using T = typename C::T;
   constexpr int NPL = C::NPL;
-  __shared__ T s_aop[C::DR ? C::kDriftTable : 1];
+  __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = C::sub_of(threadIdx.x);
   int64_t task = C::task_of(lane);
@@ -63,8 +66,9 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C::T> A) {
   LaneParams<C> L;
   L.load(A.P, sub);
   if constexpr (C::DR) {
-    stage_drift<C>(A.P.aop, s_aop);
+    stage_drift<C>(A.P.aop, A.P.d, s_aop);
     L.aop = s_aop;
+    L.set_dl(s_aop + C::kDriftTable);
   }
   T x[NPL], v[1][NPL], phi[1], rho[1], yg[1][NPL], yp[1][NPL];
   load_row<C>(A.x + b * n, n, sub, x);
@@ -192,7 +196,7 @@ __device__ __forceinline__ void attempt_values(const SolveArgs<typename C::T>& A
   if constexpr (sizeof(typename C::T) == 4) {
     const bool need = ending && status != HJ_ST_DIVERGED;
     if (A.cert_fp64 && wave_if<C>(need)) {
-      using C64 = Cfg<double, C::NPL, C::LPT, C::MK, C::DR>;
+      using C64 = Cfg<double, C::NPL, C::LPT, C::MK, C::DR, false>;
       const Problem<double>& P64 = tc.P64(A);
       LaneParams<C64> L64;
       L64.load(P64, sub);
@@ -302,7 +306,7 @@ template <class C>
 __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
   constexpr int NPL = C::NPL;
-  __shared__ T s_aop[C::DR ? C::kDriftTable : 1];
+  __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = C::sub_of(threadIdx.x);
   int64_t task = C::task_of(lane);
@@ -314,8 +318,9 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
   TaskCtx<C, false> tc;
   tc.L.load(A.P, sub);
   if constexpr (C::DR) {
-    stage_drift<C>(A.P.aop, s_aop);
+    stage_drift<C>(A.P.aop, A.P.d, s_aop);
     tc.L.aop = s_aop;
+    tc.L.set_dl(s_aop + C::kDriftTable);
   }
   tc.bind(A, live != 0 ? task : 0, sub);
   const int n = A.P.n;
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
   using T = typename C::T;
   constexpr int NPL = C::NPL;
   static_assert(!(MULTI && C::DR), "batched instances carry no drift");
-  __shared__ T s_aop[C::DR ? C::kDriftTable : 1];
+  __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = C::sub_of(threadIdx.x);
   int64_t task = C::task_of(lane);
@@ -425,8 +430,9 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
   TaskCtx<C, MULTI> tc;
   if constexpr (!MULTI) tc.L.load(A.P, sub);
   if constexpr (C::DR) {
-    stage_drift<C>(A.P.aop, s_aop);
+    stage_drift<C>(A.P.aop, A.P.d, s_aop);
     tc.L.aop = s_aop;
+    tc.L.set_dl(s_aop + C::kDriftTable);
   }
   tc.bind(A, live != 0 ? task : 0, sub);
   T v[NPL], g[NPL];
