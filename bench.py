@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--no-cd", action="store_true", help="skip the central-FD comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
+    ap.add_argument("--launch", type=json.loads, default=None,
+                    help='launch configuration of the descent as JSON, e.g. '
+                         '\'{"lanes_per_task": 1, "ckpt_K": 16}\', instead of tuning')
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a device copy run first (counter calibration)")
     args = ap.parse_args()
@@ -307,7 +310,10 @@ def main():
         }
     else:
         log(f"workload {wl.name}: B={wl.B} G={wl.G} n={wl.n} N={wl.nsteps}")
-        cfg = {} if args.no_tune else tune.tune(wl, verbose=True)
+        if args.launch is not None:
+            cfg = dict(args.launch)
+        else:
+            cfg = {} if args.no_tune else tune.tune(wl, verbose=True)
         log(f"launch configuration: {cfg or 'library default'}")
         mode_name = "adjoint GD" if wl.mode == W.GD_ADJ else "central-FD CD"
         wall, kern, host = run_gpu(wl, args.steps, args.warmup, mode_name, cfg)

@@ -280,8 +280,8 @@ template <class C> struct LaneParams {
     ia2p = P.ia2;
     aop = P.aop;
   }
-  // The FP64 matrix-core kernels read d from LDS (element 4k + sub is the
-  // lane's slot k) at every use, through a pointer the compiler cannot see
+  // The FP64 matrix-core descent kernel reads d from LDS (element 4k + sub
+  // is the lane's slot k) at every use, through a pointer the compiler cannot see
   // through: held in registers for the whole kernel, as it would hoist
   // them, the per-lane weights are what spills first on that layout, and
   // the reloads then wait behind the checkpoint stores (5% of the n = 32

@@ -47,8 +47,15 @@ __device__ __forceinline__ void stage_drift(const typename C::T* table, const ty
 // ---------------------------------------------------------------------------
 // objective evaluation (and exact gradient)
 // ---------------------------------------------------------------------------
-template <class C>
-__global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C::T> A) {
+// The evaluation and coordinate-descent kernels keep d in registers: the LDS
+// weights (Cfg::DL) pay off in the descent kernel's adjoint sweeps only, and
+// cost the forward-only coordinate descent a third of its speed (measured).
+template <class C0>
+using NoDl = Cfg<typename C0::T, C0::NPL, C0::LPT, C0::MK, C0::DR, false>;
+
+template <class C0>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C0::T> A) {
+  using C = NoDl<C0>;
   using T = typename C::T;
   constexpr int NPL = C::NPL;
   __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
@@ -302,8 +309,9 @@ __device__ __forceinline__ int64_t next_task(const SolveArgs<typename C::T>& A, 
 // iteration = one sweep over the n coordinates; the step halves when a trial
 // fails the step test)
 // ---------------------------------------------------------------------------
-template <class C>
-__global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C::T> A) {
+template <class C0>
+__global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C0::T> A) {
+  using C = NoDl<C0>;
   using T = typename C::T;
   constexpr int NPL = C::NPL;
   __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
