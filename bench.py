@@ -63,19 +63,27 @@ def algorithmic_flops(wl, slot_fwd, slot_bwd):
         float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps, dr)
 
 
+def _code_only(text):
+    """C/C++ source without comments and blank lines (the sources hold no
+    comment markers inside string literals)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def source_digest():
-    """Digest of the kernel sources and the C header (identifies the build
-    that counter measurements were taken on)."""
+    """Digest of the code of the kernel sources and the C header, comments
+    left out (identifies the build that counter measurements were taken
+    on)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1704_02524_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "hj.h"), "rb") as fh:
-        h.update(fh.read())
+    paths = [os.path.join(d, f) for f in sorted(os.listdir(d)) if f.endswith((".hip", ".hpp"))]
+    for path in paths + [os.path.join(ROOT, "include", "hj.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -225,7 +225,9 @@ typedef struct hj_batch_plan_s *hj_batch;
  * lane groups take (instance, point, guess) tasks from a queue, longest
  * instances first, and a finished group takes the next task.  The whole
  * sequence (queue resets, the descent launches, the selection) is captured
- * into a hipGraph that hj_batch_run replays; device pointers are fixed at
+ * into a hipGraph that hj_batch_run replays, the shape groups as parallel
+ * branches (they share no memory; one stream per group is created for the
+ * capture, at the default priority); device pointers are fixed at
  * planning, their contents may change between runs.  opts supplies the
  * shared options (formula, quadrature, dtype, iterations, tolerances; mode
  * must be HJ_GD_ADJ).  The plan owns its device scratch.  Errors as in
