@@ -27,6 +27,13 @@ namespace hj {
 // ---------------------------------------------------------------------------
 // math helpers
 // ---------------------------------------------------------------------------
+// Fused multiply-add in the operands' own precision (__builtin_fma is the
+// double one: on floats it converts to double and back around an FP64 FMA).
+__device__ __forceinline__ double fmaT(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Coefficients 1/j! (j = 13 .. 2) of the Taylor polynomial of expm1, in
 // constant memory so that the wave-uniform loads land in scalar registers and
 // every Horner step is one v_fma_f64 with a scalar operand.
@@ -44,23 +51,23 @@ __device__ __forceinline__ double expm1_neg(double y) {
   const double ln2_lo = 1.90821492927058770002e-10;  // ln 2 - ln2_hi
   const double inv_ln2 = 1.44269504088896338700e+00;
   const double k = __builtin_rint(y * inv_ln2);
-  double f = __builtin_fma(-k, ln2_hi, y);
-  f = __builtin_fma(-k, ln2_lo, f);
+  double f = fmaT(-k, ln2_hi, y);
+  f = fmaT(-k, ln2_lo, f);
   double p = kExpm1Coef[0];
 #pragma unroll
-  for (int j = 1; j < 12; ++j) p = __builtin_fma(p, f, kExpm1Coef[j]);
-  p = __builtin_fma(p * f, f, f);                // f + f^2 (1/2 + ...)
+  for (int j = 1; j < 12; ++j) p = fmaT(p, f, kExpm1Coef[j]);
+  p = fmaT(p * f, f, f);                // f + f^2 (1/2 + ...)
   const double s = __builtin_ldexp(1.0, (int)k); // exact; 0 for very negative k
-  return __builtin_fma(s, p, s - 1.0);
+  return fmaT(s, p, s - 1.0);
 }
 
 // a / b for b in [1, 2]: hardware reciprocal, one Newton step and one
 // residual correction of the quotient (error about one ulp).
 __device__ __forceinline__ double div_1_2(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
-  r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+  r = fmaT(fmaT(-b, r, 1.0), r, r);
   const double q = a * r;
-  return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+  return fmaT(fmaT(-b, q, a), r, q);
 }
 
 // tanh in FP64 from expm1: tanh|z| = -e / (2 + e), e = expm1(-2|z|) in
@@ -408,9 +415,9 @@ __device__ __forceinline__ T dot2(const T (&a)[NPL], const T (&b)[NPL]) {
 #pragma unroll
   for (int k = 1; k < NPL; ++k) {
     if (k & 1)
-      s1 = __builtin_fma(a[k], b[k], s1);
+      s1 = fmaT(a[k], b[k], s1);
     else
-      s0 = __builtin_fma(a[k], b[k], s0);
+      s0 = fmaT(a[k], b[k], s0);
   }
   return s0 + s1;
 }
@@ -498,16 +505,16 @@ __device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const 
         T ag0 = s == 0 ? g[t][k] : ag[t][k], ap0 = s == 0 ? p[t][k] : ap[t][k];
         T gb = g[t][k], pb = p[t][k];
         if constexpr (C::DR) {
-          ag0 = __builtin_fma(-wb, AG[t][k], ag0);
-          ap0 = __builtin_fma(wb, ATP[t][k], ap0);
-          gb = __builtin_fma(-cn, AG[t][k], gb);
-          pb = __builtin_fma(cn, ATP[t][k], pb);
+          ag0 = fmaT(-wb, AG[t][k], ag0);
+          ap0 = fmaT(wb, ATP[t][k], ap0);
+          gb = fmaT(-cn, AG[t][k], gb);
+          pb = fmaT(cn, ATP[t][k], pb);
         }
-        ag[t][k] = __builtin_fma(ag_c, dp[t][k], ag0);
-        ap[t][k] = __builtin_fma(ap_c, G[t][k], ap0);
+        ag[t][k] = fmaT(ag_c, dp[t][k], ag0);
+        ap[t][k] = fmaT(ap_c, G[t][k], ap0);
         if (s < 3) {
-          Pp[t][k] = __builtin_fma(pn_c, G[t][k], pb);
-          G[t][k] = __builtin_fma(gn_c, dp[t][k], gb);
+          Pp[t][k] = fmaT(pn_c, G[t][k], pb);
+          G[t][k] = fmaT(gn_c, dp[t][k], gb);
         }
       }
     }
@@ -720,16 +727,16 @@ __device__ __forceinline__ void vjp_stage(const Problem<typename C::T>& P, const
     matvec2<C>(L.aop, 1, kg, ATk, 0, kp, Ak);
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
-      const T og = __builtin_fma(al, kp[k], __builtin_fma(ag, G[k], -ATk[k]));
-      const T op = __builtin_fma(ap, dp[k], __builtin_fma(-S.m, L.dk(k) * kg[k], Ak[k]));
+      const T og = fmaT(al, kp[k], fmaT(ag, G[k], -ATk[k]));
+      const T op = fmaT(ap, dp[k], fmaT(-S.m, L.dk(k) * kg[k], Ak[k]));
       kg[k] = og;
       kp[k] = op;
     }
   } else {
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
-      const T og = __builtin_fma(al, kp[k], ag * G[k]);
-      const T op = __builtin_fma(ap, dp[k], -S.m * (L.dk(k) * kg[k]));
+      const T og = fmaT(al, kp[k], ag * G[k]);
+      const T op = fmaT(ap, dp[k], -S.m * (L.dk(k) * kg[k]));
       kg[k] = og;
       kp[k] = op;
     }
@@ -768,16 +775,16 @@ __device__ __forceinline__ void reverse_step_stored(const Problem<typename C::T>
       for (int k = 0; k < NPL; ++k) {
         const T gs = s ? YG[s - 1][k] : g[k];
         const T ps = s ? YP[s - 1][k] : p[k];
-        YG[s][k] = __builtin_fma(gn_c, L.dk(k) * ps, __builtin_fma(-cn, AG[k], g[k]));
-        YP[s][k] = __builtin_fma(pn_c, gs, __builtin_fma(cn, ATP[k], p[k]));
+        YG[s][k] = fmaT(gn_c, L.dk(k) * ps, fmaT(-cn, AG[k], g[k]));
+        YP[s][k] = fmaT(pn_c, gs, fmaT(cn, ATP[k], p[k]));
       }
     } else {
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         const T gs = s ? YG[s - 1][k] : g[k];
         const T ps = s ? YP[s - 1][k] : p[k];
-        YG[s][k] = __builtin_fma(gn_c, L.dk(k) * ps, g[k]);
-        YP[s][k] = __builtin_fma(pn_c, gs, p[k]);
+        YG[s][k] = fmaT(gn_c, L.dk(k) * ps, g[k]);
+        YP[s][k] = fmaT(pn_c, gs, p[k]);
       }
     }
     S[s + 1] = stage_scalars<C>(P, L, YG[s], YP[s]);
@@ -853,8 +860,8 @@ __device__ __forceinline__ void reverse_step_lean(const Problem<typename C::T>& 
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       const T gs = G[k], ps = Pp[k];
-      G[k] = __builtin_fma(gn_c, L.dk(k) * ps, g[k]);
-      Pp[k] = __builtin_fma(pn_c, gs, p[k]);
+      G[k] = fmaT(gn_c, L.dk(k) * ps, g[k]);
+      Pp[k] = fmaT(pn_c, gs, p[k]);
     }
     S[s + 1] = stage_scalars<C>(P, L, G, Pp);
   }
@@ -886,8 +893,8 @@ __device__ __forceinline__ void reverse_step_lean(const Problem<typename C::T>& 
 #pragma unroll
         for (int k = 0; k < NPL; ++k) {
           const T gs = G[k], ps = Pp[k];
-          G[k] = __builtin_fma(gn_c, L.dk(k) * ps, g[k]);
-          Pp[k] = __builtin_fma(pn_c, gs, p[k]);
+          G[k] = fmaT(gn_c, L.dk(k) * ps, g[k]);
+          Pp[k] = fmaT(pn_c, gs, p[k]);
         }
       }
     }

@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
 #pragma unroll
       for (int k = 0; k < NPL; ++k) {
         gm = nanmax(gm, dabs(g[k]));
-        vt[0][k] = __builtin_fma(-alpha, g[k], v[k]);
+        vt[0][k] = fmaT(-alpha, g[k], v[k]);
       }
       smax = alpha * cmax<C>(gm);
       gg = csum<C>(dot2<NPL>(g, g));
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
         T a = alpha;
         asm volatile("" : "+v"(a));
 #pragma unroll
-        for (int k = 0; k < NPL; ++k) v[k] = __builtin_fma(-a, g[k], v[k]);
+        for (int k = 0; k < NPL; ++k) v[k] = fmaT(-a, g[k], v[k]);
       }
       phi = ft[0];
       rho = rt[0];
