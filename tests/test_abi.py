@@ -126,3 +126,21 @@ def test_drift_limits_are_reported():
     A[3, 4] = np.inf
     rc, msg = _call_solve(wl.with_(A=A))
     assert rc == -1 and "finite" in msg
+
+
+def test_device_code_keeps_fp32_arithmetic_in_fp32():
+    """Device code takes fused multiply-adds through the precision-matched
+    helper: the bare builtin is the double one, and on float operands it
+    converts to double and back around an FP64 FMA (it used to make two
+    thirds of the FP32 kernels' instructions conversions and FP64 FMAs)."""
+    import os
+    import re
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1704_02524_amd", "csrc")
+    for name in ("hj_device.hpp", "hj_kernels.hpp"):
+        with open(os.path.join(csrc, name)) as f:
+            code = f.read()
+        uses = [m.start() for m in re.finditer(r"__builtin_fma\(", code)]
+        helper = code.find("__device__ __forceinline__ double fmaT(")
+        # the only bare use is inside the double overload of the helper
+        assert all(0 <= helper < u < helper + 200 for u in uses), (name, len(uses))
