@@ -70,6 +70,19 @@ __device__ __forceinline__ double div_1_2(double a, double b) {
   return fmaT(fmaT(-b, q, a), r, q);
 }
 
+// 1 / b for b >= 1 (no denormal results) the same way, in the operand's
+// precision: about one ulp in five instructions, where a correctly rounded
+// division takes about ten.
+__device__ __forceinline__ double recip_ge1(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fmaT(fmaT(-b, r, 1.0), r, r);
+  return fmaT(fmaT(-b, r, 1.0), r, r);
+}
+__device__ __forceinline__ float recip_ge1(float b) {
+  const float r = __builtin_amdgcn_rcpf(b);
+  return fmaT(fmaT(-b, r, 1.0f), r, r);
+}
+
 // tanh in FP64 from expm1: tanh|z| = -e / (2 + e), e = expm1(-2|z|) in
 // (-1, 0].  |z| is clamped to 20 (tanh(20) rounds to 1), which keeps the
 // code branch-free.
@@ -375,7 +388,7 @@ __device__ __forceinline__ void speed(const Problem<typename C::T>& P, typename 
     c1 = P.kappa * P.inv_s * sech2;
     if (NEED2) c2 = T(-2) * P.kappa * P.inv_s * P.inv_s * th * sech2;
   } else {
-    const T q = T(1) / (T(1) + r);
+    const T q = recip_ge1(T(1) + r);  // r >= 0
     c = T(1) + P.kappa * r * q;
     c1 = P.kappa * q * q;
     if (NEED2) c2 = T(-2) * P.kappa * q * q * q;
