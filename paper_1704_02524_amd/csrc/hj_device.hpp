@@ -56,8 +56,8 @@ __device__ __forceinline__ double expm1_neg(double y) {
   double p = kExpm1Coef[0];
 #pragma unroll
   for (int j = 1; j < 12; ++j) p = fmaT(p, f, kExpm1Coef[j]);
-  p = fmaT(p * f, f, f);                // f + f^2 (1/2 + ...)
-  const double s = __builtin_ldexp(1.0, (int)k); // exact; 0 for very negative k
+  p = fmaT(p * f, f, f);                          // f + f^2 (1/2 + ...)
+  const double s = __builtin_ldexp(1.0, (int)k);  // exact; 0 for very negative k
   return fmaT(s, p, s - 1.0);
 }
 
@@ -239,10 +239,10 @@ struct Cfg {
   // elements of the MFMA operand table of A and A^T: [2][NPL/4][NPL][64]
   static constexpr int kDriftTable = DR ? 2 * (NPL / 4) * NPL * 64 : 0;
   // waves per SIMD the descent kernel is compiled for (register budget 512 /
-  // kWaves per lane).  FP32 with at most 5 components per lane, or 16 lanes
-  // per task, fits two waves with a spill of at most a few hundred bytes
-  // that stays out of the RK4 loops, and the second wave's latency hiding
-  // pays (measured); FP64 and wider FP32 shapes lose more to spills at two
+  // kWaves per lane).  FP32 with at most 5 components per lane fits two
+  // waves without spilling, and 7 x 16 with a few hundred bytes that stay
+  // out of the RK4 loops; there the second wave's latency hiding pays
+  // (measured).  FP64 and wider FP32 shapes lose more to spills at two
   // waves than they gain.
   static constexpr int kWaves = (!DR && sizeof(T) == 4 && (LPT == 16 || NPL <= 5)) ? 2 : 1;
 };
@@ -301,10 +301,10 @@ template <class C> struct LaneParams {
     aop = P.aop;
   }
   // The FP64 matrix-core descent kernel reads d from LDS (element 4k + sub
-  // is the lane's slot k) at every use, through a pointer the compiler cannot see
-  // through: held in registers for the whole kernel, as it would hoist
-  // them, the per-lane weights are what spills first on that layout, and
-  // the reloads then wait behind the checkpoint stores (5% of the n = 32
+  // is the lane's slot k) at every use, through a pointer the compiler
+  // cannot see through: held in registers for the whole kernel, as it would
+  // hoist them, the per-lane weights are what spills first on that layout,
+  // and the reloads then wait behind the checkpoint stores (5% of the n = 32
   // solve).  In FP32 kernels, and in their FP64 certificate solve, they fit
   // and the reads would only cost (measured).
   static constexpr bool kDlds = C::DL;
