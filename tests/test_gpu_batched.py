@@ -46,8 +46,12 @@ def _batch(n_inst=8, max_points=20, dtype=W.F64, G=4):
     return [w.with_(guesses=w.guesses[:, :G].copy(), max_iter=120) for w in wls]
 
 
-def test_batched_equals_single_solves_and_graph_replays(hj):
-    wls = _batch()
+@pytest.mark.parametrize("dtype", [W.F64, W.F32])
+def test_batched_equals_single_solves_and_graph_replays(hj, dtype):
+    """The captured plan (its shape groups as concurrent graph branches)
+    gives every instance what a single solve gives it, on every replay, with
+    eager work between the replays."""
+    wls = _batch(dtype=dtype)
     plan = hj.BatchPlan(wls)
     info = plan.info()
     assert info["tasks"] == sum(w.B * w.G for w in wls)
