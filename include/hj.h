@@ -35,11 +35,14 @@
  *  - Parameter arrays inside hj_h_params / hj_j_params are HOST pointers to
  *    double and are copied during the call.
  *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null stream)
- *    and the call returns without waiting; results are valid once that stream
- *    has completed.  Scratch memory comes from opts->workspace when it is
- *    given (ws_bytes >= hj_workspace_size), else from an allocation the
- *    library caches per device and grows as needed; calls that share that
- *    cache must be ordered on one stream.
+ *    and the call returns without waiting for the device: the parameter
+ *    arrays are passed to the device inside kernel arguments, so the host
+ *    memory they occupy may be reused as soon as the call returns.  Results
+ *    are valid once that stream has completed.  Scratch memory comes from
+ *    opts->workspace when it is given (ws_bytes >= hj_workspace_size), else
+ *    from an allocation the library caches per device and grows as needed
+ *    (growing it waits for the device once); calls that share that cache
+ *    must be ordered on one stream.
  *  - Return value: HJ_OK (0) or a negative HJ_E* code; the message of the
  *    last error on the calling thread is returned by hj_last_error().  No
  *    entry point aborts the process.
@@ -138,6 +141,14 @@ typedef struct {
                              lanes                                          */
     int32_t max_groups;   /* persistent schedule: at most this many lane
                              groups (0: as many as the device holds)       */
+    int32_t fp64_continue; /* HJ_F32 with cert_fp64 and HJ_GD_ADJ: a slot
+                             whose FP32 attempt ends finite but fails the
+                             FP64 certificate continues in FP64 -- gradient
+                             descent from that attempt's v (step reset to
+                             alpha0, up to max_iter iterations), then FP64
+                             restarts from its remaining guesses -- in a
+                             second launch over the handed-off slots only.
+                             0: the FP32 attempts alone decide.            */
 } hj_opts;
 
 enum {
@@ -244,7 +255,9 @@ int32_t hj_batch_info(hj_batch plan, int64_t *tasks, int64_t *groups, int32_t *l
 /* Release a plan (waits for its work to finish). */
 int32_t hj_batch_free(hj_batch plan);
 
-/* Scratch bytes hj_solve / hj_eval need for B points of G slots. */
+/* Scratch bytes hj_solve / hj_eval need for B points of G slots, with the
+ * schedule hj_solve picks on the current device (persistent launches hold
+ * checkpoints for resident lane groups only). */
 size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps,
                          const hj_opts *opts);
 

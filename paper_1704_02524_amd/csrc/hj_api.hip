@@ -86,41 +86,97 @@ size_t drift_table_len(int npl) { return (size_t)2 * (npl / 4) * npl * 64; }
 // MFMA returns block row 4 r + l / 16 in register r of lane l, the FP32 one
 // row 4 (l / 16) + r; row() reorders the FP32 rows so that in both cases
 // register r of lane `sub` receives component 16 ib + 4 r + sub, which that
-// lane owns (slot 4 ib + r).
+// lane owns (slot 4 ib + r).  Built on the device from A (row-major, FP64).
 template <typename T>
-std::vector<T> drift_table(const double* A, int n, int npl) {
+__global__ __launch_bounds__(256) void k_drift_table(const double* A, int n, int npl, T* table) {
   const int NB = npl / 4;
-  std::vector<T> t(drift_table_len(npl), T(0));
-  for (int m = 0; m < 2; ++m)
-    for (int ib = 0; ib < NB; ++ib)
-      for (int kb = 0; kb < npl; ++kb)
-        for (int l = 0; l < 64; ++l) {
-          const int i = l % 16;
-          const int ri = sizeof(T) == 8 ? i : 4 * (i % 4) + i / 4;
-          const int row = 16 * ib + ri, col = 4 * kb + l / 16;
-          double val = 0.0;
-          if (row < n && col < n) val = (m == 0) ? A[row * n + col] : A[col * n + row];
-          t[(((size_t)m * NB + ib) * npl + kb) * 64 + l] = (T)val;
-        }
-  return t;
+  const int total = 2 * NB * npl * 64;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int l = idx % 64, kb = (idx / 64) % npl, ib = (idx / (64 * npl)) % NB;
+  const int m = idx / (64 * npl * NB);
+  const int i = l % 16;
+  const int ri = sizeof(T) == 8 ? i : 4 * (i % 4) + i / 4;
+  const int row = 16 * ib + ri, col = 4 * kb + l / 16;
+  double val = 0.0;
+  if (row < n && col < n) val = (m == 0) ? A[row * n + col] : A[col * n + row];
+  table[idx] = (T)val;
 }
+
+// Stream-ordered upload of small host data (the per-component parameters,
+// the drift matrix) into device memory through kernel arguments: the
+// runtime copies a launch's argument block when the launch is enqueued, so
+// the host needs no staging buffer, returns without waiting, and may reuse
+// its memory at once; the copy is ordered after earlier work on the stream.
+constexpr int kUploadWords = 736;  // 2944 bytes of payload per launch
+struct Upload {
+  uint64_t off;  // destination offset in 32-bit words
+  uint32_t n;    // words used in w
+  uint32_t pad_;
+  uint32_t w[kUploadWords];
+};
+__global__ __launch_bounds__(256) void k_upload(uint32_t* dst, Upload u) {
+  for (uint32_t i = threadIdx.x; i < u.n; i += blockDim.x) dst[u.off + i] = u.w[i];
+}
+
+class Uploader {
+ public:
+  Uploader(void* dst, hipStream_t st) : dst_(static_cast<uint32_t*>(dst)), st_(st) {
+    u_.off = 0;
+    u_.n = 0;
+    u_.pad_ = 0;
+  }
+  template <typename T> void put(T v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized values");
+    uint32_t w[sizeof(T) / 4];
+    std::memcpy(w, &v, sizeof(T));
+    for (uint32_t x : w) {
+      if (u_.n == kUploadWords) (void)flush();
+      u_.w[u_.n++] = x;
+    }
+  }
+  // continue at a byte offset (a multiple of 4) at or after the current one
+  void seek(size_t byte_off) {
+    (void)flush();
+    u_.off = byte_off / 4;
+  }
+  hipError_t flush() {
+    if (u_.n > 0 && err_ == hipSuccess) {
+      hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, st_, dst_, u_);
+      err_ = hipGetLastError();
+    }
+    u_.off += u_.n;
+    u_.n = 0;
+    return err_;
+  }
+
+ private:
+  uint32_t* dst_;
+  hipStream_t st_;
+  Upload u_;
+  hipError_t err_ = hipSuccess;
+};
 
 // Layout of the scratch memory of one call.
 struct WsLayout {
   size_t params = 0, slots = 0, queue = 0, ck = 0, seg = 0, total = 0;
   size_t stride = 0;  // lanes of the SoA checkpoint arrays
+  // FP64 continuation of FP32 slots: hand-off list, its counters (entries,
+  // continuation queue), FP64 checkpoints over stride64 lanes
+  size_t handoff = 0, cont_ctr = 0, ck64 = 0, seg64 = 0, stride64 = 0;
 };
 
-// lanes: lanes that hold adjoint checkpoints (0: one lane group per task)
+// lanes: lanes that hold adjoint checkpoints (0: one lane group per task);
+// cont_lanes: lanes of the FP64 continuation launch (0: none)
 WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
-                bool grad, bool solve, size_t lanes = 0) {
+                bool grad, bool solve, size_t lanes = 0, size_t cont_lanes = 0) {
   WsLayout L;
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
   const size_t BG = (size_t)B * (size_t)G;
   size_t off = 0;
   L.params = off;
   off += align_up((size_t)s.npad() * 3 * (8 + tsz), 256);
-  if (s.dr) off += align_up(drift_table_len(s.npl) * (8 + tsz), 256);
+  if (s.dr) off += align_up(drift_table_len(s.npl) * (8 + tsz) + (size_t)n * n * 8, 256);
   if (solve) {
     L.slots = off;
     off += align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * (size_t)n * tsz, 256);
@@ -128,15 +184,26 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
     off += 256;
   }
   const bool need_adj = grad || (solve && mode == HJ_GD_ADJ);
+  const int Kc = std::max(1, std::min(K, nsteps));
+  const size_t nck = (size_t)((nsteps + Kc - 1) / Kc) + 1;
   if (need_adj) {
     if (lanes == 0) lanes = align_up(BG * (size_t)s.lpt, 256);
-    const int Kc = std::max(1, std::min(K, nsteps));
-    const size_t nck = (size_t)((nsteps + Kc - 1) / Kc) + 1;
     L.stride = lanes;
     L.ck = off;
     off += align_up(nck * 2 * s.npl * lanes * tsz, 256);
     L.seg = off;
     off += align_up((size_t)Kc * 2 * s.npl * lanes * tsz, 256);
+  }
+  if (solve && cont_lanes > 0) {
+    L.handoff = off;
+    off += align_up(BG * 8, 256);
+    L.cont_ctr = off;
+    off += 256;
+    L.stride64 = cont_lanes;
+    L.ck64 = off;
+    off += align_up(nck * 2 * s.npl * cont_lanes * 8, 256);
+    L.seg64 = off;
+    off += align_up((size_t)Kc * 2 * s.npl * cont_lanes * 8, 256);
   }
   L.total = off;
   return L;
@@ -240,40 +307,56 @@ hj::Problem<T> make_problem(const hj_h_params* H, const hj_j_params* J, int n, d
   return P;
 }
 
-// Stage d, a^2, 1/a^2 (in T and in double) into the params region, followed
-// with drift by the operand tables of A (in T and in double).  The copy is
-// ordered on the stream after any earlier call's kernels that read the
-// region, and completes before the host buffer goes out of scope.
+// Stage d, a^2, 1/a^2 (in T and in double) into the params region through
+// kernel-argument uploads, followed with drift by A (FP64) and the MFMA
+// operand tables built from it on the device (in double and in T).  Every
+// step is enqueued on the stream, ordered after earlier calls' kernels that
+// read the region; the host does not wait.
 template <typename T>
 int stage_params(const hj_h_params* H, const hj_j_params* J, int n, const Shape& s,
                  char* region, hipStream_t st, const T** dT, const double** dD,
                  const T** aT, const double** aD) {
   const int npad = s.npad();
-  HostParams<T> pt = host_params<T>(H, J, n, npad);
-  HostParams<double> pd = host_params<double>(H, J, n, npad);
   const size_t plen = (size_t)npad * 3 * (sizeof(T) + 8);
   const size_t tlen = s.dr ? drift_table_len(s.npl) : 0;
-  std::vector<char> buf(plen + tlen * (sizeof(T) + 8));
-  char* q = buf.data();
-  std::memcpy(q, pt.d.data(), npad * sizeof(T));
-  std::memcpy(q + npad * sizeof(T), pt.a2.data(), npad * sizeof(T));
-  std::memcpy(q + 2 * npad * sizeof(T), pt.ia2.data(), npad * sizeof(T));
-  char* q2 = q + 3 * npad * sizeof(T);
-  std::memcpy(q2, pd.d.data(), npad * 8);
-  std::memcpy(q2 + npad * 8, pd.a2.data(), npad * 8);
-  std::memcpy(q2 + 2 * npad * 8, pd.ia2.data(), npad * 8);
-  if (tlen) {
-    const std::vector<double> t64 = drift_table<double>(H->A, n, s.npl);
-    const std::vector<T> tT = drift_table<T>(H->A, n, s.npl);
-    std::memcpy(q + plen, t64.data(), tlen * 8);
-    std::memcpy(q + plen + tlen * 8, tT.data(), tlen * sizeof(T));
+  Uploader up(region, st);
+  // d, a^2, 1/a^2 in T, then in double; padding: d = 0, a = 1
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q < 3; ++q)
+      for (int i = 0; i < npad; ++i) {
+        double val = (q == 0) ? 0.0 : 1.0;
+        if (i < n) {
+          const double a = J->a[i];
+          val = q == 0 ? H->d[i] : q == 1 ? a * a : 1.0 / (a * a);
+        }
+        if (pass == 0)
+          up.put<T>((T)val);
+        else
+          up.put<double>(val);
+      }
   }
-  HJ_HIP(hipMemcpyAsync(region, buf.data(), buf.size(), hipMemcpyHostToDevice, st));
-  HJ_HIP(hipStreamSynchronize(st));
+  if (tlen) {
+    // A after the two tables
+    up.seek(plen + tlen * (8 + sizeof(T)));
+    for (int i = 0; i < n * n; ++i) up.put<double>(H->A[i]);
+  }
+  HJ_HIP(up.flush());
   *dT = reinterpret_cast<const T*>(region);
   *dD = reinterpret_cast<const double*>(region + 3 * npad * sizeof(T));
-  *aD = tlen ? reinterpret_cast<const double*>(region + plen) : nullptr;
-  *aT = tlen ? reinterpret_cast<const T*>(region + plen + tlen * 8) : nullptr;
+  *aD = nullptr;
+  *aT = nullptr;
+  if (tlen) {
+    double* t64 = reinterpret_cast<double*>(region + plen);
+    T* tT = reinterpret_cast<T*>(region + plen + tlen * 8);
+    const double* Ad = reinterpret_cast<const double*>(region + plen + tlen * (8 + sizeof(T)));
+    const unsigned grid = (unsigned)((tlen + 255) / 256);
+    hipLaunchKernelGGL(k_drift_table<double>, dim3(grid), dim3(256), 0, st, Ad, n, s.npl, t64);
+    HJ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_drift_table<T>, dim3(grid), dim3(256), 0, st, Ad, n, s.npl, tT);
+    HJ_HIP(hipGetLastError());
+    *aD = t64;
+    *aT = tT;
+  }
   return HJ_OK;
 }
 
@@ -357,6 +440,67 @@ hipError_t dispatch_eval(const Shape& s, int mk, const hj::EvalArgs<T>& A, hipSt
   return hipErrorInvalidValue;
 }
 
+// The FP64 continuation kernels of an FP32 lane shape.
+hipError_t dispatch_continue(const Shape& s, int mk, const hj::ContArgs<float>& A, bool multi,
+                             int64_t grid_groups, hipStream_t st) {
+  if (s.dr) {
+#define HJ_DCASE(NPL)                                                                        \
+  if (s.npl == NPL)                                                                          \
+    return mk == HJ_M_TANH                                                                   \
+               ? hj::launch_continue<hj::Cfg<double, NPL, 4, HJ_M_TANH, true>>(A, multi,     \
+                                                                             grid_groups, st) \
+               : hj::launch_continue<hj::Cfg<double, NPL, 4, HJ_M_RAT, true>>(A, multi,      \
+                                                                            grid_groups, st);
+    HJ_FOR_EACH_DRIFT_NPL(HJ_DCASE)
+#undef HJ_DCASE
+    return hipErrorInvalidValue;
+  }
+#define HJ_CASE(NPL, LPT)                                                                      \
+  if (s.npl == NPL && s.lpt == LPT)                                                            \
+    return mk == HJ_M_TANH ? hj::launch_continue<hj::Cfg<double, NPL, LPT, HJ_M_TANH>>(        \
+                                 A, multi, grid_groups, st)                                    \
+                           : hj::launch_continue<hj::Cfg<double, NPL, LPT, HJ_M_RAT>>(         \
+                                 A, multi, grid_groups, st);
+  HJ_FOR_EACH_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return hipErrorInvalidValue;
+}
+
+int64_t dispatch_resident_continue(const Shape& s, int mk) {
+  if (s.dr) {
+#define HJ_DCASE(NPL)                                                                    \
+  if (s.npl == NPL)                                                                      \
+    return mk == HJ_M_TANH                                                               \
+               ? hj::resident_continue_groups<hj::Cfg<double, NPL, 4, HJ_M_TANH, true>>() \
+               : hj::resident_continue_groups<hj::Cfg<double, NPL, 4, HJ_M_RAT, true>>();
+    HJ_FOR_EACH_DRIFT_NPL(HJ_DCASE)
+#undef HJ_DCASE
+    return 0;
+  }
+#define HJ_CASE(NPL, LPT)                                                          \
+  if (s.npl == NPL && s.lpt == LPT)                                                \
+    return mk == HJ_M_TANH                                                         \
+               ? hj::resident_continue_groups<hj::Cfg<double, NPL, LPT, HJ_M_TANH>>() \
+               : hj::resident_continue_groups<hj::Cfg<double, NPL, LPT, HJ_M_RAT>>();
+  HJ_FOR_EACH_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return 0;
+}
+
+// Lane groups of the FP64 continuation launch of an FP32 GD solve over ntask
+// slots (0: no continuation).
+int64_t continue_groups(const Shape& s, int mk, const hj_opts* o, int64_t ntask) {
+  if (o->dtype != HJ_F32 || o->mode != HJ_GD_ADJ || !o->cert_fp64 || !o->fp64_continue)
+    return 0;
+  int64_t g = dispatch_resident_continue(s, mk);
+  if (o->max_groups > 0) g = std::min<int64_t>(g, o->max_groups);
+  return std::max<int64_t>(1, std::min(g, ntask));
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ULL;
+}
+
 // The lane shape of a problem, or an error naming what is not compiled.
 int shape_for(const hj_h_params* H, int n, int lpt, bool f32, Shape& s) {
   const bool drift = H->A != nullptr;
@@ -370,6 +514,22 @@ int shape_for(const hj_h_params* H, int n, int lpt, bool f32, Shape& s) {
                                    " lanes per task for n = " + std::to_string(n));
 }
 
+// Scratch layout of hj_solve with the schedule it will use: the lane groups
+// of a persistent descent launch (0: one per task) and of the FP64
+// continuation (0: none).  A persistent launch holds checkpoints for its
+// resident lanes only.
+template <typename T>
+WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nsteps,
+                      const hj_opts* o, int64_t* groups, int64_t* cgroups) {
+  const int K = std::max(1, std::min(o->ckpt_K, nsteps));
+  const int64_t ntask = B * (int64_t)G;
+  *groups = schedule_groups<T>(s, mk, o->mode, o->schedule, ntask, o->max_groups);
+  *cgroups = continue_groups(s, mk, o, ntask);
+  const size_t ck_lanes = *groups > 0 ? align_up((size_t)*groups * s.lpt, 256) : 0;
+  const size_t cont_lanes = *cgroups > 0 ? align_up((size_t)*cgroups * s.lpt, 256) : 0;
+  return layout(s, n, B, G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes, cont_lanes);
+}
+
 template <typename T>
 int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B, int n,
             double t, int nsteps, const hj_guesses* gs, const hj_opts* o, double* out_u,
@@ -380,11 +540,8 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
   const int64_t ntask = B * (int64_t)gs->G;
-  const int64_t groups =
-      schedule_groups<T>(s, kernel_mk(H), o->mode, o->schedule, ntask, o->max_groups);
-  // a persistent launch holds checkpoints for its resident lanes only
-  const size_t ck_lanes = groups > 0 ? align_up((size_t)groups * s.lpt, 256) : 0;
-  WsLayout WL = layout(s, n, B, gs->G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes);
+  int64_t groups = 0, cgroups = 0;
+  WsLayout WL = solve_layout<T>(s, kernel_mk(H), n, B, gs->G, nsteps, o, &groups, &cgroups);
   if ((size_t)B * gs->G * s.lpt > (size_t)UINT32_MAX * 128)
     return fail(HJ_EINVAL, "B * G too large for one launch");
   void* ws = nullptr;
@@ -445,9 +602,37 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   A.queue = groups > 0 ? reinterpret_cast<unsigned long long*>(base + WL.queue) : nullptr;
   A.inst = nullptr;
   A.n_inst = 0;
+  A.handoff = nullptr;
+  A.handoff_n = nullptr;
+  unsigned long long* ctr = nullptr;
+  if (cgroups > 0) {
+    A.handoff = reinterpret_cast<int64_t*>(base + WL.handoff);
+    ctr = reinterpret_cast<unsigned long long*>(base + WL.cont_ctr);
+    A.handoff_n = ctr;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, ctr, 16);
+    HJ_HIP(hipGetLastError());
+  }
 
   if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
   HJ_HIP(dispatch_solve<T>(s, kernel_mk(H), A, o->mode, groups, st));
+  if constexpr (sizeof(T) == 4) {
+    if (cgroups > 0) {
+      hj::ContArgs<float> CA;
+      CA.S = A;
+      CA.max_iter = o->max_iter;
+      CA.K = K;
+      CA.alpha0 = o->alpha0;
+      CA.eps_step = o->eps_step;
+      CA.acc_rel = o->acc_rel;
+      CA.armijo_c = o->armijo_c;
+      CA.v_max = o->v_max;
+      CA.ck = reinterpret_cast<double*>(base + WL.ck64);
+      CA.seg = reinterpret_cast<double*>(base + WL.seg64);
+      CA.stride = WL.stride64;
+      CA.queue = ctr + 8;
+      HJ_HIP(dispatch_continue(s, kernel_mk(H), CA, false, cgroups, st));
+    }
+  }
   if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
   HJ_HIP(hj::launch_select<T>(B, gs->G, n, o->formula, A.out.phi, A.out.cert, A.out.v, out_u,
                               static_cast<T*>(out_argopt), out_cert, st));
@@ -513,6 +698,7 @@ hj_opts default_opts() {
   o.v_max = 1e6;
   o.acc_rel = 64 * 2.220446049250313e-16;
   o.armijo_c = 0.1;
+  o.fp64_continue = 1;
   return o;
 }
 
@@ -569,6 +755,9 @@ struct LaunchGroup {
   int max_steps = 0;
   // byte offsets in the plan memory
   size_t params = 0, table = 0, slots = 0, queue = 0, ck = 0, seg = 0, stride = 0;
+  // FP64 continuation of FP32 slots (cgroups = 0: none)
+  int64_t cgroups = 0;
+  size_t handoff = 0, cont_ctr = 0, ck64 = 0, seg64 = 0, stride64 = 0;
 };
 
 template <typename T>
@@ -602,6 +791,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     int64_t res = dispatch_resident<T>(g.s, g.mk, HJ_GD_ADJ);
     if (o->max_groups > 0) res = std::min<int64_t>(res > 0 ? res : g.tasks, o->max_groups);
     g.groups = std::max<int64_t>(1, std::min(res > 0 ? res : g.tasks, g.tasks));
+    g.cgroups = continue_groups(g.s, g.mk, o, g.tasks);
   }
   // memory layout
   const int Kmax = std::max(1, o->ckpt_K);
@@ -627,6 +817,17 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     off += align_up(nck * 2 * g.s.npl * g.stride * tsz, 256);
     g.seg = off;
     off += align_up((size_t)K * 2 * g.s.npl * g.stride * tsz, 256);
+    if (g.cgroups > 0) {
+      g.handoff = off;
+      off += align_up((size_t)g.tasks * 8, 256);
+      g.cont_ctr = off;
+      off += 256;
+      g.stride64 = align_up((size_t)g.cgroups * g.s.lpt, 256);
+      g.ck64 = off;
+      off += align_up(nck * 2 * g.s.npl * g.stride64 * 8, 256);
+      g.seg64 = off;
+      off += align_up((size_t)K * 2 * g.s.npl * g.stride64 * 8, 256);
+    }
     (void)n;
   }
   if (hipMalloc(&plan->mem, std::max<size_t>(off, 256)) != hipSuccess) {
@@ -717,6 +918,9 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     A.queue = reinterpret_cast<unsigned long long*>(base + g.queue);
     A.inst = reinterpret_cast<const hj::InstDesc<T>*>(base + g.table);
     A.n_inst = (int)g.inst.size();
+    A.handoff = g.cgroups > 0 ? reinterpret_cast<int64_t*>(base + g.handoff) : nullptr;
+    A.handoff_n =
+        g.cgroups > 0 ? reinterpret_cast<unsigned long long*>(base + g.cont_ctr) : nullptr;
     args.push_back(A);
   }
   // capture the launch groups into a graph as parallel branches (fork from
@@ -743,7 +947,29 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     const LaunchGroup& g = lg[gi];
     const hj::SolveArgs<T>& A = args[gi];
     hipStream_t st = gi == 0 ? plan->cap : plan->branch[gi - 1];
-    err = dispatch_solve<T>(g.s, g.mk, A, HJ_GD_ADJ, g.groups, st);
+    if (g.cgroups > 0) {
+      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, A.handoff_n, 16);
+      err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = dispatch_solve<T>(g.s, g.mk, A, HJ_GD_ADJ, g.groups, st);
+    if constexpr (sizeof(T) == 4) {
+      if (err == hipSuccess && g.cgroups > 0) {
+        hj::ContArgs<float> CA;
+        CA.S = A;
+        CA.max_iter = o->max_iter;
+        CA.K = A.K;
+        CA.alpha0 = o->alpha0;
+        CA.eps_step = o->eps_step;
+        CA.acc_rel = o->acc_rel;
+        CA.armijo_c = o->armijo_c;
+        CA.v_max = o->v_max;
+        CA.ck = reinterpret_cast<double*>(base + g.ck64);
+        CA.seg = reinterpret_cast<double*>(base + g.seg64);
+        CA.stride = g.stride64;
+        CA.queue = A.handoff_n + 8;
+        err = dispatch_continue(g.s, g.mk, CA, true, g.cgroups, st);
+      }
+    }
     if (err == hipSuccess)
       err = hj::launch_select_batched<T>(A.inst, A.n_inst, g.points, A.P.n, o->formula,
                                          A.out.phi, A.out.cert, A.out.v, st);
@@ -829,9 +1055,15 @@ size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const 
   for (int drift = 0; drift < 2; ++drift) {
     Shape s{};
     if (!pick_shape(n, o.lanes_per_task, drift != 0, o.dtype == HJ_F32, s)) continue;
-    WsLayout a = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, false, true);
+    for (int mk : {HJ_M_TANH, HJ_M_RAT}) {
+      int64_t g = 0, cg = 0;
+      WsLayout a = o.dtype == HJ_F64
+                       ? solve_layout<double>(s, mk, n, B, G, nsteps, &o, &g, &cg)
+                       : solve_layout<float>(s, mk, n, B, G, nsteps, &o, &g, &cg);
+      need = std::max(need, a.total);
+    }
     WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
-    need = std::max(need, std::max(a.total, b.total));
+    need = std::max(need, b.total);
   }
   return need;
 }

@@ -272,25 +272,24 @@ __device__ __forceinline__ void write_slot(const SolveArgs<typename C::T>& A,
 // Step test: the trial must realise the fraction armijo_c of the decrease
 // alpha <g, d> its gradient predicts, up to a rounding allowance acc_rel |F|
 // (armijo_c = 0: no ascent).
-template <typename T>
-__device__ __forceinline__ bool accept_step(const SolveArgs<T>& A, T trial, T cur, T decrease) {
-  return trial <= cur - A.armijo_c * decrease + A.acc_rel * dabs(cur);
+template <class AT, typename T>
+__device__ __forceinline__ bool accept_step(const AT& A, T trial, T cur, T decrease) {
+  return trial <= cur - T(A.armijo_c) * decrease + T(A.acc_rel) * dabs(cur);
 }
 
 // Stop tests at the end of an iteration, in the order of the reference.
-template <class C>
-__device__ __forceinline__ int stop_status(const SolveArgs<typename C::T>& A,
-                                           const typename C::T (&v)[C::NPL],
+template <class C, class AT>
+__device__ __forceinline__ int stop_status(const AT& A, const typename C::T (&v)[C::NPL],
                                            typename C::T phi, typename C::T smax,
                                            typename C::T alpha, int it) {
   using T = typename C::T;
-  const T alpha_floor = A.alpha0 * T(9.094947017729282e-13);  // alpha0 * 2^-40
+  const T alpha_floor = T(A.alpha0) * T(9.094947017729282e-13);  // alpha0 * 2^-40
   T vmax = T(0);
 #pragma unroll
   for (int k = 0; k < C::NPL; ++k) vmax = nanmax(vmax, dabs(v[k]));
   vmax = cmax<C>(vmax);
-  if (!isfinite(phi) || !(vmax <= A.v_max)) return HJ_ST_DIVERGED;
-  if (smax < A.eps_step) return HJ_ST_CONVERGED;
+  if (!isfinite(phi) || !(vmax <= T(A.v_max))) return HJ_ST_DIVERGED;
+  if (smax < T(A.eps_step)) return HJ_ST_CONVERGED;
   if (alpha < alpha_floor) return HJ_ST_STALLED;
   if (it >= A.max_iter) return HJ_ST_MAXITER;
   return -1;
@@ -514,8 +513,14 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
     double phi64, rho64;
     attempt_values<C, MULTI>(A, tc, sub, v, phi, rho, status, ending, phi64, rho64);
     if (ending) {
-      if (end_attempt<C, MULTI>(A, tc, sub, task, v, phi64, rho64, status, it, att, best)) {
+      bool done = end_attempt<C, MULTI>(A, tc, sub, task, v, phi64, rho64, status, it, att, best);
+      // FP64 continuation: the first finite attempt the FP64 certificate
+      // rejects ends the slot here (best.cert == 0 only then: earlier
+      // attempts were not finite) and goes to the hand-off list
+      const bool handoff = sizeof(T) == 4 && A.handoff != nullptr && best.cert == 0;
+      if (done || handoff) {
         write_slot<C, MULTI>(A, tc, sub, task, best);
+        if (handoff && sub == 0) A.handoff[atomicAdd(A.handoff_n, 1ULL)] = task;
         task = next_task<C>(A, sub);
         att = 0;
         if (task < 0) {
@@ -530,6 +535,221 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
       }
       load_row<C>(tc.g0 + (int64_t)att * tc.P(A).n, tc.P(A).n, sub, v);
       it = -1;
+    }
+    if constexpr (C::DR) {
+      if (!wave_if<C>(live != 0)) break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 continuation of handed-off FP32 slots (same lane shape, FP64
+// arithmetic): the slot's record gives its state after the FP32 attempt
+// (attempts used, counts, the attempt's v); the descent resumes from that v
+// with the step size reset, and an attempt the certificate still rejects is
+// followed by FP64 restarts from the slot's remaining guesses, exactly as in
+// k_solve_gd.  Every lane group pops list indices until the list (whose
+// length the FP32 launch left in device memory) is exhausted.
+// ---------------------------------------------------------------------------
+template <class C> struct ContCtx {
+  Problem<double> P;
+  LaneParams<C> L;
+  double x[C::NPL];
+  const float* g0;  // guesses of the task: [R+1, n]
+  int R;
+  template <bool MULTI>
+  __device__ __forceinline__ void bind(const SolveArgs<float>& S, int64_t task, int sub) {
+    const float* xb;
+    if constexpr (MULTI) {
+      int lo = 0, hi = S.n_inst - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.inst[mid].task0 <= task)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const InstDesc<float>& I = S.inst[lo];
+      P = I.P64;
+      const int64_t lt = task - I.task0;
+      R = I.R;
+      xb = I.x + (lt / I.G) * P.n;
+      g0 = I.guesses + lt * (int64_t)(I.R + 1) * P.n;
+    } else {
+      P = S.P64;
+      R = S.R;
+      xb = S.x + (task / S.G) * P.n;
+      g0 = S.guesses + task * (int64_t)(S.R + 1) * P.n;
+    }
+    if constexpr (!C::DR) L.load(P, sub);
+#pragma unroll
+    for (int k = 0; k < C::NPL; ++k) {
+      const int i = C::comp(sub, k);
+      x[k] = (i < P.n) ? (double)xb[i] : 0.0;
+    }
+  }
+  // an FP32 row as FP64 components (0 beyond n)
+  __device__ __forceinline__ void load_f32(const float* base, int sub, double (&out)[C::NPL]) const {
+#pragma unroll
+    for (int k = 0; k < C::NPL; ++k) {
+      const int i = C::comp(sub, k);
+      out[k] = (i < P.n) ? (double)base[i] : 0.0;
+    }
+  }
+};
+
+template <class C, bool MULTI>
+__global__ __launch_bounds__(256, 1) void k_continue_gd(ContArgs<float> A) {
+  static_assert(sizeof(typename C::T) == 8, "the continuation runs in FP64");
+  static_assert(!(MULTI && C::DR), "batched instances carry no drift");
+  constexpr int NPL = C::NPL;
+  const SolveArgs<float>& S = A.S;
+  __shared__ double s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
+  const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int sub = C::sub_of(threadIdx.x);
+  const int64_t count = (int64_t)*S.handoff_n;
+  int64_t idx = pop_task<C>(A.queue, sub);
+  int live = idx < count ? 1 : 0;
+  if constexpr (!C::DR) {
+    if (!live) return;
+  }
+  ContCtx<C> tc;
+  if constexpr (C::DR) {
+    stage_drift<C>(S.P64.aop, S.P64.d, s_aop);
+    tc.L.load(S.P64, sub);
+    tc.L.aop = s_aop;
+    tc.L.set_dl(s_aop + C::kDriftTable);
+    if (!wave_if<C>(live != 0)) return;  // after the block's only barrier
+  }
+  const int vs = S.P.n;  // row stride of the slot records
+  int64_t task = live ? S.handoff[idx] : 0;
+  SlotBest best;
+  double v[NPL], g[NPL];
+  int att = 0, it = -1;
+  // resume a handed-off slot: bind its problem and point, read its record
+  auto resume = [&]() {
+    tc.template bind<MULTI>(S, task, sub);
+    best.phi = S.out.phi[task];
+    best.rho = S.out.rho[task];
+    best.cert = S.out.cert[task];
+    best.status = S.out.status[task];
+    best.iters = S.out.iters[task];
+    best.attempts = S.out.attempts[task];
+    best.n_fwd = S.out.n_fwd[task];
+    best.n_bwd = S.out.n_bwd[task];
+    att = best.attempts - 1;
+    tc.load_f32(S.out.v + task * vs, sub, v);
+    it = -1;
+  };
+  resume();
+#pragma unroll
+  for (int k = 0; k < NPL; ++k) g[k] = 0.0;
+  double alpha = A.alpha0, phi = 0.0, rho = 0.0;
+  while (true) {
+    const bool start = it < 0;
+    const Problem<double>& P = tc.P;
+    double vt[1][NPL], ft[1], rt[1], smax = 0.0, gg = 0.0;
+    if (start) {
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) vt[0][k] = v[k];
+    } else {
+      double gm = 0.0;
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        gm = nanmax(gm, dabs(g[k]));
+        vt[0][k] = fmaT(-alpha, g[k], v[k]);
+      }
+      smax = alpha * cmax<C>(gm);
+      gg = csum<C>(dot2<NPL>(g, g));
+    }
+    forward<C, 1, true>(P, tc.L, tc.x, vt, ft, rt, A.ck, A.stride, lane, A.K);
+    best.n_fwd += 1;
+    const bool acc = start || accept_step(A, ft[0], phi, alpha * gg);
+    if (acc) {
+      if (!start) {
+        double a = alpha;
+        asm volatile("" : "+v"(a));
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) v[k] = fmaT(-a, g[k], v[k]);
+      }
+      phi = ft[0];
+      rho = rt[0];
+    } else {
+      alpha *= 0.5;
+    }
+    const bool need_grad = acc && isfinite(phi);
+    if (wave_if<C>(need_grad)) {
+      double gt[NPL], gx[NPL];
+      backward<C>(P, tc.L, tc.x, v, A.ck, A.seg, A.stride, lane, A.K, gt, gx);
+      if (need_grad) {
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) g[k] = gt[k];
+        best.n_bwd += 1;
+      }
+    }
+    int status = -1;
+    if (start) {
+      it = 0;
+      alpha = A.alpha0;
+      if (!isfinite(phi))
+        status = HJ_ST_DIVERGED;
+      else if (A.max_iter == 0)
+        status = HJ_ST_MAXITER;
+    } else {
+      ++it;
+      status = stop_status<C>(A, v, phi, smax, alpha, it);
+    }
+    if (live != 0 && status >= 0) {
+      // end of an attempt, as end_attempt: FP64 objective and residual
+      best.iters += it;
+      best.attempts = att + 1;
+      const bool fin = (status != HJ_ST_DIVERGED) && isfinite(phi);
+      const double r64 = (status == HJ_ST_DIVERGED) ? __builtin_nan("") : rho;
+      const bool certified = fin && (r64 <= S.cert_tol);
+      if (certified || (fin && (best.cert < 0 || phi < best.phi))) {
+        best.phi = phi;
+        best.rho = r64;
+        best.cert = certified ? 1 : 0;
+        best.status = status;
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+          const int i = C::comp(sub, k);
+          if (i < P.n) S.out.v[task * vs + i] = (float)v[k];
+        }
+      }
+      if (certified || att + 1 > tc.R) {
+        if (best.cert < 0) {
+#pragma unroll
+          for (int k = 0; k < NPL; ++k) {
+            const int i = C::comp(sub, k);
+            if (i < P.n) S.out.v[task * vs + i] = __builtin_nanf("");
+          }
+        }
+        if (sub == 0) {
+          S.out.phi[task] = best.phi;
+          S.out.rho[task] = best.rho;
+          S.out.status[task] = best.status;
+          S.out.cert[task] = best.cert;
+          S.out.iters[task] = best.iters;
+          S.out.attempts[task] = best.attempts;
+          S.out.n_fwd[task] = best.n_fwd;
+          S.out.n_bwd[task] = best.n_bwd;
+        }
+        idx = pop_task<C>(A.queue, sub);
+        if (idx >= count) {
+          if constexpr (!C::DR) break;
+          live = 0;
+        } else {
+          task = S.handoff[idx];
+          resume();
+          continue;
+        }
+      } else {
+        // restart in FP64 from the slot's next guess
+        ++att;
+        tc.load_f32(tc.g0 + (int64_t)att * P.n, sub, v);
+        it = -1;
+      }
     }
     if constexpr (C::DR) {
       if (!wave_if<C>(live != 0)) break;
@@ -675,6 +895,39 @@ hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, int64_t gri
 }
 
 template <class C>
+int64_t resident_continue_groups() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_continue_gd<C, false>, 256, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (int64_t)cus * per_cu * (256 / C::LPT);
+}
+
+template <class C>
+hipError_t launch_continue(const ContArgs<float>& A, bool multi, int64_t grid_groups,
+                           hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (grid_groups * C::LPT + block - 1) / block;
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, st, A.queue, 0ULL);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (multi) {
+    if constexpr (C::DR) {
+      return hipErrorInvalidValue;  // batches carry no drift
+    } else {
+      hipLaunchKernelGGL((k_continue_gd<C, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
+    }
+  } else {
+    hipLaunchKernelGGL((k_continue_gd<C, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+template <class C>
 hipError_t launch_eval(const EvalArgs<typename C::T>& A, hipStream_t st) {
   const int64_t threads = A.B * A.G * C::LPT;
   const int block = 256;
@@ -737,3 +990,15 @@ hipError_t launch_scatter_diag(const InstDesc<T>* inst, int n_inst, int64_t tota
 #define HJ_INSTANTIATE_DRIFT(T, NPL)              \
   HJ_INSTANTIATE_DRIFT_MK(T, NPL, HJ_M_TANH)      \
   HJ_INSTANTIATE_DRIFT_MK(T, NPL, HJ_M_RAT)
+// The FP64 continuation kernels of the FP32 lane shape (NPL, LPT), without
+// and with linear drift.
+#define HJ_INSTANTIATE_CONT_MK(NPL, LPT, MK, DR)                                           \
+  template hipError_t hj::launch_continue<hj::Cfg<double, NPL, LPT, MK, DR>>(              \
+      const hj::ContArgs<float>&, bool, int64_t, hipStream_t);                              \
+  template int64_t hj::resident_continue_groups<hj::Cfg<double, NPL, LPT, MK, DR>>();
+#define HJ_INSTANTIATE_CONT(NPL, LPT)                     \
+  HJ_INSTANTIATE_CONT_MK(NPL, LPT, HJ_M_TANH, false)      \
+  HJ_INSTANTIATE_CONT_MK(NPL, LPT, HJ_M_RAT, false)
+#define HJ_INSTANTIATE_CONT_DRIFT(NPL)                 \
+  HJ_INSTANTIATE_CONT_MK(NPL, 4, HJ_M_TANH, true)      \
+  HJ_INSTANTIATE_CONT_MK(NPL, 4, HJ_M_RAT, true)

@@ -60,6 +60,25 @@ template <typename T> struct SolveArgs {
   // batched instances (nullptr: the single problem above)
   const InstDesc<T>* inst;
   int n_inst;
+  // FP32 runs with an FP64 continuation (null otherwise): a slot whose FP32
+  // attempt ends finite but rejected by the FP64 certificate is handed off,
+  // its record written and its task index appended to `handoff`
+  int64_t* handoff;                 // [ntask]
+  unsigned long long* handoff_n;    // entries in handoff (starts at 0)
+};
+
+// FP64 continuation of the slots an FP32 launch handed off: each resumes the
+// descent in FP64 from its FP32 result (then restarts in FP64 from its
+// remaining guesses), and its record is updated in place.
+template <typename TS> struct ContArgs {
+  SolveArgs<TS> S;          // the FP32 launch: problems (P64 used), inputs,
+                            // records, instance table, hand-off list
+  int max_iter, K;
+  double alpha0, eps_step, acc_rel, armijo_c, v_max;
+  double* ck;               // FP64 adjoint checkpoints over `stride` lanes
+  double* seg;
+  size_t stride;
+  unsigned long long* queue;  // next index into S.handoff (starts at 0)
 };
 
 template <typename T> struct EvalArgs {
@@ -90,6 +109,14 @@ template <class C>
 int64_t resident_groups(int mode);
 template <class C>
 hipError_t launch_eval(const EvalArgs<typename C::T>& A, hipStream_t st);
+// The FP64 continuation of an FP32 launch's hand-off list: grid_groups lane
+// groups of the FP64 configuration C pop list indices from A.queue (reset to
+// 0 by this call).  multi: the FP32 launch was batched.
+template <class C>
+hipError_t launch_continue(const ContArgs<float>& A, bool multi, int64_t grid_groups,
+                           hipStream_t st);
+template <class C>
+int64_t resident_continue_groups();
 template <typename T>
 hipError_t launch_select(int64_t B, int G, int n, int formula, const double* s_phi,
                          const int32_t* s_cert, const T* s_v, double* out_u, T* out_arg,

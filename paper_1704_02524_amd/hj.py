@@ -47,7 +47,7 @@ class Opts(C.Structure):
                 ("armijo_c", C.c_double),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("schedule", C.c_int32),
-                ("max_groups", C.c_int32)]
+                ("max_groups", C.c_int32), ("fp64_continue", C.c_int32)]
 
 SCHED_AUTO, SCHED_STATIC, SCHED_PERSISTENT = 0, 1, 2
 
@@ -146,7 +146,7 @@ def make_opts(wl, stream: Optional[torch.cuda.Stream] = None, events=None, **ove
               max_iter=wl.max_iter, ckpt_K=wl.ckpt_K, cert_fp64=int(wl.cert_fp64),
               alpha0=wl.alpha0, fd_sigma=wl.fd_sigma, eps_step=wl.eps_step,
               cert_tol=wl.cert_tol, v_max=wl.v_max, acc_rel=wl.acc_rel,
-              armijo_c=wl.armijo_c)
+              armijo_c=wl.armijo_c, fp64_continue=int(wl.fp64_continue))
     kw.update(over)
     o = Opts()
     for k, v in kw.items():

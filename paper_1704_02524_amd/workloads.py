@@ -77,6 +77,9 @@ class Workload:
     acc_rel: float = 64 * 2.220446049250313e-16
     armijo_c: float = ARMIJO_DEFAULT
     cert_fp64: bool = True
+    # FP32 adjoint descent: continue in FP64 an attempt whose FP32 result the
+    # FP64 certificate rejects (the FP64 reference's attempt sequence)
+    fp64_continue: bool = True
     seed: int = 0
 
     @property

@@ -100,7 +100,8 @@ def test_batched_fp32(hj):
     for w, out in zip(wls, outs):
         got = _host(out)
         ref = Oracle.from_workload(w).solve(w.x[:2], w.guesses[:2], Oracle.opts_from_workload(w))
-        fin = (ref["cert"] >= 0) & (got["cert"][:2] >= 0)
+        np.testing.assert_array_equal(got["cert"][:2], ref["cert"])
+        fin = ref["cert"] >= 0
         err = np.abs(got["u"][:2][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
         assert err.max(initial=0.0) <= 1e-4, (w.name, err)
     plan.free()
@@ -115,7 +116,9 @@ def test_persistent_many_tasks_per_group_equals_static(hj, dtype, mode, lpt):
     launch gives it, bit for bit: nothing of a finished task carries over."""
     wl = W.c1_hopf_n10(B=96)
     if dtype == W.F32:
-        wl = W._as_dtype(wl.with_(eps_step=1e-6, cert_tol=1e-4))
+        # FP32 restarts: without the FP64 continuation an attempt the
+        # certificate rejects restarts in FP32
+        wl = W._as_dtype(wl.with_(eps_step=1e-6, cert_tol=1e-4, fp64_continue=False))
     wl = wl.with_(max_iter=60, mode=mode)
     if mode == W.CD_FD:
         wl = wl.with_(guesses=wl.guesses[:, :4].copy(), max_iter=20)
@@ -142,3 +145,43 @@ def test_batched_persistent_equals_single(hj):
             np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
         np.testing.assert_allclose(got["u"], ref["u"], rtol=1e-13, atol=1e-13)
     plan.free()
+
+
+@pytest.mark.parametrize("lpt", [1, 2])
+def test_fp64_continuation_persistent_equals_static(hj, lpt):
+    """FP32 descent whose rejected attempts continue in FP64: the hand-off
+    list is filled in whatever order the lane groups finish, and a
+    persistent launch of 64 groups (and a continuation launch of 64 groups)
+    still gives every slot the static launch's result bit for bit."""
+    wl = W._as_dtype(W.c1_hopf_n10(B=96).with_(eps_step=1e-6, cert_tol=1e-6, max_iter=60))
+    x, g = hj.device_inputs(wl)
+    a = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_STATIC))
+    b = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_PERSISTENT,
+                       max_groups=64))
+    # some slots were handed off: without the continuation they end otherwise
+    c = _host(hj.solve(wl, x, g, lanes_per_task=lpt, schedule=hj.SCHED_STATIC,
+                       fp64_continue=0))
+    assert (c["slot_iters"] != a["slot_iters"]).any()
+    for k in a:
+        np.testing.assert_array_equal(np.nan_to_num(a[k]), np.nan_to_num(b[k]), err_msg=k)
+
+
+def test_fp64_continuation_certifies_what_the_reference_certifies(hj):
+    """Long-horizon FP32 instances of the batched workload (n = 4 and 8,
+    t about 1.8), where FP32 descent alone stops above the tolerance on some
+    slots: with the FP64 continuation every point's certificate flag is the
+    FP64 reference's, and u agrees to 1e-4."""
+    wls = W.c2_batched(dtype=W.F32)
+    for i, npts in ((60, 32), (7, 32), (33, 12)):
+        wl = wls[i].subset(0, npts)
+        x, g = hj.device_inputs(wl)
+        without = _host(hj.solve(wl, x, g, fp64_continue=0))
+        got = _host(hj.solve(wl, x, g))
+        ref = Oracle.from_workload(wl).solve(wl.x, wl.guesses, Oracle.opts_from_workload(wl))
+        print(f"instance {i}: uncertified slots FP32 only {(without['slot_cert'] != 1).sum()}, "
+              f"with continuation {(got['slot_cert'] != 1).sum()}, "
+              f"reference {(ref['slot_cert'] != 1).sum()}")
+        np.testing.assert_array_equal(got["cert"], ref["cert"], err_msg=wl.name)
+        fin = ref["cert"] >= 0
+        err = np.abs(got["u"][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
+        assert err.max(initial=0.0) <= 1e-4, (wl.name, err)
