@@ -194,6 +194,26 @@ int32_t hj_solve(int32_t H_kind, const hj_h_params *H, int32_t J_kind, const hj_
                  double *out_u, void *out_argopt, int32_t *out_cert,
                  const hj_slot_diag *diag);
 
+/* hj_solve_noalloc -- hj_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, checks and results as hj_solve; the
+ * scratch memory is a fixed array of HJ_NOALLOC_BYTES that the library holds
+ * on every device it runs on (until the process ends), so the call allocates
+ * nothing.  opts->workspace must be NULL.  When the requested schedule needs
+ * more scratch than the array holds, the solve runs persistent with fewer
+ * lane groups (results are identical); when even 64 groups do not fit (the
+ * per-slot records grow with B * G), the call returns HJ_ENOMEM with the
+ * needed size in hj_last_error().  Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (different streams, different threads) race, so order them on one
+ * stream. */
+#define HJ_NOALLOC_BYTES ((size_t)64 << 20)
+int32_t hj_solve_noalloc(int32_t H_kind, const hj_h_params *H, int32_t J_kind,
+                         const hj_j_params *J, const void *x, int64_t B, int32_t n, double t,
+                         int32_t nsteps, const hj_guesses *guesses, const hj_opts *opts,
+                         double *out_u, void *out_argopt, int32_t *out_cert,
+                         const hj_slot_diag *diag);
+
 /* hj_eval -- the discretised objective at given v (section 4.2) and,
  * optionally, its exact gradient by the discrete adjoint of the RK4 solve
  * and the quadrature.

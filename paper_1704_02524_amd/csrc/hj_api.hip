@@ -14,6 +14,13 @@
 #include "hj.h"
 #include "hj_launch.hpp"
 
+// Scratch of hj_solve_noalloc: a file-scope device array, one copy per
+// device, that the library holds until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (in host code the name is a
+// host-side stand-in, not a device address): each device's address comes
+// from hipGetSymbolAddress, taken once with that device current.
+static __device__ __align__(256) unsigned char scratch[HJ_NOALLOC_BYTES];
+
 namespace {
 
 using hj::Shape;
@@ -207,6 +214,26 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
   }
   L.total = off;
   return L;
+}
+
+// Device address of this device's copy of `scratch` (looked up on the first
+// call on the device, then kept).
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64];
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  HJ_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HJ_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HJ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HJ_EDEVICE, "hipGetSymbolAddress returned no address for the scratch");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return HJ_OK;
 }
 
 int get_workspace(const hj_opts* o, size_t need, void** out) {
@@ -1018,6 +1045,72 @@ int32_t hj_solve(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_
   if (B == 0) return HJ_OK;
   if (!x || !guesses->init || !out_u || !out_argopt || !out_cert)
     return fail(HJ_EINVAL, "x, guesses->init and the outputs are required");
+  if (o.dtype == HJ_F64)
+    return solve_t<double>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert,
+                           diag);
+  return solve_t<float>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert, diag);
+}
+
+int32_t hj_solve_noalloc(int32_t H_kind, const hj_h_params* H, int32_t J_kind,
+                         const hj_j_params* J, const void* x, int64_t B, int32_t n, double t,
+                         int32_t nsteps, const hj_guesses* guesses, const hj_opts* opts,
+                         double* out_u, void* out_argopt, int32_t* out_cert,
+                         const hj_slot_diag* diag) {
+  g_last_error.clear();
+  int rc = check_problem(H_kind, H, J_kind, J, n, t, nsteps);
+  if (rc) return rc;
+  if (B < 0) return fail(HJ_EINVAL, "B must be >= 0");
+  if (!guesses) return fail(HJ_EINVAL, "guesses are required");
+  if (guesses->G < 1 || guesses->G > HJ_MAX_G) return fail(HJ_EINVAL, "G must be in [1, 64]");
+  if (guesses->R_max < 0) return fail(HJ_EINVAL, "R_max must be >= 0");
+  hj_opts o = opts ? *opts : default_opts();
+  rc = check_opts(&o);
+  if (rc) return rc;
+  if (o.workspace)
+    return fail(HJ_EINVAL, "hj_solve_noalloc uses the library's fixed scratch: "
+                           "opts->workspace must be NULL");
+  if (B == 0) return HJ_OK;
+  if (!x || !guesses->init || !out_u || !out_argopt || !out_cert)
+    return fail(HJ_EINVAL, "x, guesses->init and the outputs are required");
+  Shape s{};
+  rc = shape_for(H, n, o.lanes_per_task, o.dtype == HJ_F32, s);
+  if (rc) return rc;
+  const int mk = kernel_mk(H);
+  const int G = guesses->G;
+  auto need_of = [&](const hj_opts& oo, int64_t* g) {
+    int64_t cg = 0;
+    return (oo.dtype == HJ_F64 ? solve_layout<double>(s, mk, n, B, G, nsteps, &oo, g, &cg)
+                               : solve_layout<float>(s, mk, n, B, G, nsteps, &oo, g, &cg))
+        .total;
+  };
+  int64_t groups = 0;
+  size_t need = need_of(o, &groups);
+  if (need > HJ_NOALLOC_BYTES) {
+    // a persistent launch holds checkpoints for its lane groups only: halve
+    // the groups until the layout fits (results do not depend on them)
+    int64_t mg = groups;
+    if (mg <= 0)
+      mg = std::min<int64_t>(o.dtype == HJ_F64 ? dispatch_resident<double>(s, mk, o.mode)
+                                               : dispatch_resident<float>(s, mk, o.mode),
+                             B * (int64_t)G);
+    o.schedule = HJ_SCHED_PERSISTENT;
+    while (need > HJ_NOALLOC_BYTES && mg > 64) {
+      mg = std::max<int64_t>(64, mg / 2);
+      o.max_groups = (int32_t)mg;
+      need = need_of(o, &groups);
+    }
+    if (need > HJ_NOALLOC_BYTES)
+      return fail(HJ_ENOMEM, "hj_solve_noalloc: this solve needs " + std::to_string(need) +
+                                 " bytes of scratch even with 64 lane groups; the fixed "
+                                 "scratch holds " +
+                                 std::to_string((size_t)HJ_NOALLOC_BYTES) +
+                                 " bytes (use hj_solve, or fewer points)");
+  }
+  void* ptr = nullptr;
+  rc = noalloc_scratch(&ptr);
+  if (rc) return rc;
+  o.workspace = ptr;
+  o.ws_bytes = HJ_NOALLOC_BYTES;
   if (o.dtype == HJ_F64)
     return solve_t<double>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert,
                            diag);

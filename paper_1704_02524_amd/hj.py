@@ -85,6 +85,8 @@ def lib():
                                C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                                C.POINTER(Guesses), C.POINTER(Opts), C.c_void_p, C.c_void_p,
                                C.c_void_p, C.POINTER(SlotDiag)]
+        L.hj_solve_noalloc.restype = C.c_int32
+        L.hj_solve_noalloc.argtypes = L.hj_solve.argtypes
         L.hj_eval.restype = C.c_int32
         L.hj_eval.argtypes = [C.c_int32, C.POINTER(HParams), C.c_int32, C.POINTER(JParams),
                               C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
@@ -168,8 +170,10 @@ def device_inputs(wl, device="cuda"):
 
 
 def solve(wl, x: torch.Tensor, guesses: torch.Tensor, diag: bool = True,
-          stream: Optional[torch.cuda.Stream] = None, out=None, events=None, **opt_over):
-    """hj_solve on device tensors x [B, n], guesses [B, G, R+1, n].
+          stream: Optional[torch.cuda.Stream] = None, out=None, events=None,
+          noalloc: bool = False, **opt_over):
+    """hj_solve (hj_solve_noalloc with noalloc=True) on device tensors
+    x [B, n], guesses [B, G, R+1, n].
 
     Returns a dict of device tensors: u [B] (float64), argopt [B, n],
     cert [B] (int32) and, with diag, the per-slot records."""
@@ -204,10 +208,11 @@ def solve(wl, x: torch.Tensor, guesses: torch.Tensor, diag: bool = True,
                      _ptr(out["slot_attempts"]), _ptr(out["slot_fwd"]), _ptr(out["slot_bwd"]),
                      _ptr(out["slot_v"]))
     gs = Guesses(G, R1 - 1, _ptr(guesses))
-    rc = lib().hj_solve(HJ_H_QUADRATIC, C.byref(prob.H), HJ_J_ELLIPSOID, C.byref(prob.J),
-                        _ptr(x), B, n, float(wl.t), int(wl.nsteps), C.byref(gs), C.byref(o),
-                        _ptr(out["u"]), _ptr(out["argopt"]), _ptr(out["cert"]),
-                        C.byref(D) if D is not None else None)
+    fn = lib().hj_solve_noalloc if noalloc else lib().hj_solve
+    rc = fn(HJ_H_QUADRATIC, C.byref(prob.H), HJ_J_ELLIPSOID, C.byref(prob.J),
+            _ptr(x), B, n, float(wl.t), int(wl.nsteps), C.byref(gs), C.byref(o),
+            _ptr(out["u"]), _ptr(out["argopt"]), _ptr(out["cert"]),
+            C.byref(D) if D is not None else None)
     _check(rc)
     return out
 

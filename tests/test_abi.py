@@ -44,7 +44,8 @@ def _wl():
     return W.c1_hopf_n10(B=2)
 
 
-def _call_solve(wl, B=2, n=None, t=None, nsteps=None, G=4, R=2, xptr=1, **opt):
+def _call_solve(wl, B=2, n=None, t=None, nsteps=None, G=4, R=2, xptr=1, entry="hj_solve",
+                **opt):
     from paper_1704_02524_amd import hj
     L = hj.lib()
     prob = hj.Problem(wl)
@@ -56,7 +57,7 @@ def _call_solve(wl, B=2, n=None, t=None, nsteps=None, G=4, R=2, xptr=1, **opt):
     for k, v in opt.items():
         setattr(o, k, v)
     gs = hj.Guesses(G, R, C.c_void_p(1))
-    rc = L.hj_solve(0, C.byref(prob.H), 0, C.byref(prob.J), C.c_void_p(xptr), B,
+    rc = getattr(L, entry)(0, C.byref(prob.H), 0, C.byref(prob.J), C.c_void_p(xptr), B,
                     wl.n if n is None else n, wl.t if t is None else t,
                     wl.nsteps if nsteps is None else nsteps, C.byref(gs), C.byref(o),
                     C.c_void_p(1), C.c_void_p(1), C.c_void_p(1), None)
@@ -69,10 +70,20 @@ def _call_solve(wl, B=2, n=None, t=None, nsteps=None, G=4, R=2, xptr=1, **opt):
     (dict(R=-1), -1), (dict(B=-3), -1), (dict(dtype=7), -2), (dict(mode=5), -1),
     (dict(quad=9), -1), (dict(max_iter=-1), -1), (dict(ckpt_K=0), -1), (dict(alpha0=0.0), -1),
 ])
-def test_invalid_arguments_are_rejected(kw, code):
-    rc, msg = _call_solve(_wl(), **kw)
+@pytest.mark.parametrize("entry", ["hj_solve", "hj_solve_noalloc"])
+def test_invalid_arguments_are_rejected(kw, code, entry):
+    rc, msg = _call_solve(_wl(), entry=entry, **kw)
     assert rc == code
     assert msg
+
+
+def test_noalloc_entry_point_refuses_a_caller_workspace():
+    """hj_solve_noalloc works in the library's fixed scratch only."""
+    rc, msg = _call_solve(_wl(), entry="hj_solve_noalloc", workspace=C.c_void_p(4096),
+                          ws_bytes=1 << 20)
+    assert rc == -1 and "workspace" in msg
+    rc, msg = _call_solve(_wl(), B=0, xptr=0, entry="hj_solve_noalloc")
+    assert rc == 0 and msg == ""
 
 
 def test_zero_points_is_a_noop():
@@ -102,8 +113,6 @@ def test_unknown_kinds_and_drift_are_reported():
 def test_workspace_size_grows_with_the_problem():
     from paper_1704_02524_amd import hj
     L = hj.lib()
-    o = hj.make_opts.__wrapped__ if hasattr(hj.make_opts, "__wrapped__") else None
-    assert o is None
     small = L.hj_workspace_size(10, 16, 4, 128, None)
     big = L.hj_workspace_size(10, 4096, 16, 128, None)
     assert 0 < small < big
