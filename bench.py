@@ -63,6 +63,21 @@ def algorithmic_flops(wl, slot_fwd, slot_bwd):
         float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps, dr)
 
 
+# The hot-path scope table's own count of the same work, for comparison:
+# a stage costs F = 16 n + 4 n^2 [drift] + 12, a step 4 F + 12, a solve N
+# steps, and a gradient-descent iteration about 3.75 solves (the trial
+# evaluation, one recomputation of the checkpointed trajectory and a
+# vector-Jacobian sweep worth about 1.75 solves; 3.1 with drift, whose
+# matrix products dominate both directions alike).  Unlike the count above
+# it includes the adjoint's recomputation.
+def survey_flops(wl, slot_fwd, slot_bwd):
+    dr = wl.A is not None
+    f_st = 16 * wl.n + (4 * wl.n * wl.n if dr else 0) + 12
+    per_solve = wl.nsteps * (4 * f_st + 12)
+    bwd = 2.1 if dr else 2.75
+    return (float(slot_fwd.sum()) + bwd * float(slot_bwd.sum())) * per_solve
+
+
 def _code_only(text):
     """C/C++ source without comments and blank lines (the sources hold no
     comment markers inside string literals)."""
@@ -172,12 +187,13 @@ def run_batched(wls, steps, warmup):
     return wall, kern_ms, hosts, info
 
 
-def cpu_baseline(wls, budget_s=15.0):
-    """The FP64 reference, single-threaded, on (point, guess) slots taken in
-    order (points in turn from the instances), until about budget_s seconds
-    of work.  Rate: certified slots / G per second, i.e. point solves per
-    second when a point's G slots are solved in turn (a point counts as
-    certified once any of its slots is, so this does not overstate it)."""
+def cpu_baseline_slots(wls, budget_s=15.0):
+    """The FP64 reference, single-threaded in this process, on (point, guess)
+    slots taken in order (points in turn from the instances), until about
+    budget_s seconds of work (the batched workloads).  Rate: certified slots
+    / G per second, i.e. point solves per second when a point's G slots are
+    solved in turn (a point counts as certified once any of its slots is,
+    so this does not overstate it)."""
     from oracle.oracle import Oracle, build
     build()
     oracles = [(Oracle.from_workload(w), Oracle.opts_from_workload(w)) for w in wls]
@@ -203,12 +219,54 @@ def cpu_baseline(wls, budget_s=15.0):
         n_slots += 1
     dt = time.perf_counter() - t0
     G = wls[0].G
-    where = "the first points of the same workload" if len(wls) == 1 else \
-        f"points taken in turn from the {len(wls)} instances"
     return dict(value=n_cert / G / dt, unit="certified solves/s", cores=1, kind="oracle",
-                sample=f"{n_slots} (point, guess) slots of {where} ({dt:.1f} s, {n_cert} "
-                       f"certified), FP64 reference, 1 thread; rate = certified slots / "
-                       f"{G} guesses per second")
+                sample=f"{n_slots} (point, guess) slots of points taken in turn from the "
+                       f"{len(wls)} instances ({dt:.1f} s, {n_cert} certified), FP64 "
+                       f"reference, 1 thread; rate = certified slots / {G} guesses per second")
+
+
+def host_cores():
+    """Cores of this host's share: the affinity mask, at most 16 (the CPU
+    share of one GPU on the measurement boxes)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_points(name, budget_s, workers):
+    """The FP64 reference on whole points of a single-instance workload, in
+    `workers` processes over disjoint points (worker w: points w, w +
+    workers, ...), each until about budget_s seconds; rate = certified points
+    over the wall time of the slowest worker.  Also the one-process rate."""
+    import subprocess
+    from oracle.oracle import build
+    build()
+
+    def run(k):
+        procs = [subprocess.Popen([sys.executable, "-m", "oracle.cpu_rate", name, str(w), str(k),
+                                   str(budget_s)], cwd=ROOT, stdout=subprocess.PIPE, text=True)
+                 for w in range(k)]
+        outs = []
+        for pr in procs:
+            out, _ = pr.communicate(timeout=budget_s * 4 + 120)
+            if pr.returncode != 0:
+                raise RuntimeError(f"oracle worker failed ({pr.returncode})")
+            outs.append(json.loads(out.strip().splitlines()[-1]))
+        return outs
+
+    one = run(1)[0]
+    many = run(workers)
+    wall = max(o["seconds"] for o in many)
+    pts = sum(o["points"] for o in many)
+    cert = sum(o["certified"] for o in many)
+    return dict(value=cert / wall, unit="certified solves/s", cores=workers, kind="oracle",
+                sample=f"{pts} whole points of the same workload (all guesses and restarts), "
+                       f"{workers} processes of the FP64 reference over disjoint points, "
+                       f"{wall:.1f} s wall, {cert} certified",
+                single_thread={"value": one["certified"] / one["seconds"], "cores": 1,
+                               "points": one["points"], "seconds": one["seconds"]})
 
 
 def copy_probe(nbytes):
@@ -259,6 +317,88 @@ def build_workloads(name, points):
     raise ValueError(name)
 
 
+def roofline_of(wl, host, kern_ms, cfg, workload, kernel):
+    """The dominant kernel against its roofline: algorithmic flops of one
+    launch over its HIP-event duration (and the same on the scope table's
+    count)."""
+    from paper_1704_02524_amd import workloads as W
+    dtype = "f64" if wl.dtype == W.F64 else "f32"
+    bound = "mfma" if wl.A is not None else "alu"
+    peak = PEAK[(bound, dtype)]
+    k_s = float(np.mean(kern_ms)) / 1e3
+    flops = algorithmic_flops(wl, host["slot_fwd"], host["slot_bwd"])
+    flops_sv = survey_flops(wl, host["slot_fwd"], host["slot_bwd"])
+    achieved = flops / k_s / 1e12
+    return {
+        "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": measured_traffic(workload, cfg),
+        "kernel": kernel, "launch": cfg, "kernel_ms": float(np.mean(kern_ms)),
+        "algorithmic_flops_per_launch": flops,
+        "scope_table_count": {"flops_per_launch": flops_sv,
+                              "achieved": flops_sv / k_s / 1e12,
+                              "frac": flops_sv / k_s / 1e12 / peak},
+    }
+
+
+def cd_comparison(wl, host, wall, cd_points, tune_cd):
+    """Central-difference coordinate descent on the same GPU, on the first
+    cd_points points (all of them when None).  The speedup is the ratio of
+    certified solves per second; accuracy is compared on the points both
+    descents certify."""
+    from paper_1704_02524_amd import tune
+    from paper_1704_02524_amd import workloads as W
+    wcd = wl.with_(mode=W.CD_FD)
+    if cd_points:
+        wcd = wcd.subset(0, min(cd_points, wl.B))
+    cfg_cd = tune.tune(wcd, tune_iters=2, verbose=True) if tune_cd else {}
+    if wl.A is not None:
+        cfg_cd = {}  # the matrix-core layout has one lane shape
+    log(f"launch configuration (CD): {cfg_cd or 'library default'}")
+    wall_cd, kern_cd, host_cd = run_gpu(wcd, 1, 0, "central-FD CD", cfg_cd)
+    m = wcd.B
+    both = (host["cert"][:m] == 1) & (host_cd["cert"] == 1)
+    du = np.abs(host["u"][:m][both] - host_cd["u"][both]) / \
+        np.maximum(1, np.abs(host["u"][:m][both]))
+    tol = 1e-9 if wl.dtype == W.F64 else 1e-4
+    cert_gd = int((host["cert"] == 1).sum())
+    cert_cd = int((host_cd["cert"] == 1).sum())
+    rate_gd = cert_gd / wall
+    rate_cd = cert_cd / wall_cd
+    flops_cd = algorithmic_flops(wcd, host_cd["slot_fwd"], host_cd["slot_bwd"])
+    return {
+        "cd_fd": {
+            "points": m, "launch": cfg_cd, "ms_per_step": wall_cd * 1e3,
+            "certified_points": cert_cd, "certified_fraction": cert_cd / m,
+            "certified_fraction_adjoint": float((host["cert"][:m] == 1).mean()),
+            "value": rate_cd, "achieved_tflops": flops_cd / (kern_cd[0] / 1e3) / 1e12,
+            "points_both_certified": int(both.sum()),
+            "max_rel_u_diff_vs_adjoint": float(du.max(initial=0.0)),
+            "equal_accuracy": bool(du.max(initial=0.0) <= tol),
+            "fewer_certified_than_adjoint": bool(cert_cd < int((host["cert"][:m] == 1).sum())),
+        },
+        # certified solves per second, adjoint over central differences
+        "speedup_adjoint_vs_cd": rate_gd / rate_cd if rate_cd > 0 else None,
+    }
+
+
+def measure_single(wl, workload, steps, warmup, cfg):
+    """One single-instance workload: timed solves, certified rate, roofline."""
+    from paper_1704_02524_amd import workloads as W
+    log(f"workload {wl.name}: B={wl.B} G={wl.G} n={wl.n} N={wl.nsteps}")
+    log(f"launch configuration: {cfg or 'library default'}")
+    mode_name = "adjoint GD" if wl.mode == W.GD_ADJ else "central-FD CD"
+    wall, kern, host = run_gpu(wl, steps, warmup, mode_name, cfg)
+    n_cert = int((host["cert"] == 1).sum())
+    kernel = "k_solve_gd" if wl.mode == W.GD_ADJ else "k_solve_cd"
+    return {
+        "value": n_cert / wall, "unit": "certified solves/s", "ms_per_step": wall * 1e3,
+        "dtype": "f64" if wl.dtype == W.F64 else "f32",
+        "config": {"workload": describe(wl), "points": wl.B, "guesses": wl.G, "n": wl.n,
+                   "nsteps": wl.nsteps, "certified_points": n_cert},
+        "roofline": roofline_of(wl, host, kern, cfg, workload, kernel),
+    }, wall, host
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +412,12 @@ def main():
                          "on all points by default; other workloads only with this option)")
     ap.add_argument("--no-cd", action="store_true", help="skip the central-FD comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
+    ap.add_argument("--no-n32", action="store_true",
+                    help="skip the n=32 drift record of the default (n=10) run")
+    ap.add_argument("--n32-cd-points", type=int, default=8192,
+                    help="points of the n=32 central-FD comparison")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of CPU reference work per process")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--launch", type=json.loads, default=None,
                     help='launch configuration of the descent as JSON, e.g. '
@@ -296,96 +442,93 @@ def main():
     wl = wls[0]
     batched = len(wls) > 1
     dtype = "f64" if wl.dtype == W.F64 else "f32"
-    bound = "mfma" if wl.A is not None else "alu"
-    peak = PEAK[(bound, dtype)]
     if batched:
         log(f"workload {args.workload}: {len(wls)} instances, "
             f"{sum(w.B for w in wls)} points, {sum(w.B * w.G for w in wls)} tasks")
         wall, kern, hosts, info = run_batched(wls, args.steps, args.warmup)
         cfg = {"plan": info}
         n_cert = int(sum((h["cert"] == 1).sum() for h in hosts))
+        k_s = float(np.mean(kern)) / 1e3
         flops = sum(algorithmic_flops(w, h["slot_fwd"], h["slot_bwd"])
                     for w, h in zip(wls, hosts))
-        kernel = "k_solve_gd (batched launches of one graph)"
-        config = {
-            "workload": f"{args.workload}: {len(wls)} Hopf instances, n in "
-                        f"{sorted({w.n for w in wls})}, t~U[0.2,2], N in "
-                        f"{sorted({w.nsteps for w in wls})}, {sum(w.B for w in wls)} points "
-                        f"in total, {wl.G} guesses, adjoint gradient descent, one captured "
-                        f"graph, {dtype.upper()}",
-            "instances": len(wls), "points": int(sum(w.B for w in wls)), "guesses": wl.G,
-            "certified_points": n_cert,
+        flops_sv = sum(survey_flops(w, h["slot_fwd"], h["slot_bwd"])
+                       for w, h in zip(wls, hosts))
+        peak = PEAK[("alu", dtype)]
+        rec = {
+            "value": n_cert / wall, "unit": "certified solves/s", "ms_per_step": wall * 1e3,
+            "dtype": dtype,
+            "config": {
+                "workload": f"{args.workload}: {len(wls)} Hopf instances, n in "
+                            f"{sorted({w.n for w in wls})}, t~U[0.2,2], N in "
+                            f"{sorted({w.nsteps for w in wls})}, {sum(w.B for w in wls)} "
+                            f"points in total, {wl.G} guesses, adjoint gradient descent, one "
+                            f"captured graph, {dtype.upper()}",
+                "instances": len(wls), "points": int(sum(w.B for w in wls)), "guesses": wl.G,
+                "certified_points": n_cert},
+            "roofline": {
+                "bound": "alu", "achieved": flops / k_s / 1e12, "peak": peak,
+                "unit": "TFLOP/s", "frac": flops / k_s / 1e12 / peak,
+                "traffic": measured_traffic(args.workload, cfg),
+                "kernel": "k_solve_gd (batched launches of one graph)", "launch": cfg,
+                "kernel_ms": float(np.mean(kern)), "algorithmic_flops_per_launch": flops,
+                "scope_table_count": {"flops_per_launch": flops_sv,
+                                      "achieved": flops_sv / k_s / 1e12,
+                                      "frac": flops_sv / k_s / 1e12 / peak}},
         }
     else:
-        log(f"workload {wl.name}: B={wl.B} G={wl.G} n={wl.n} N={wl.nsteps}")
         if args.launch is not None:
             cfg = dict(args.launch)
         else:
             cfg = {} if args.no_tune else tune.tune(wl, verbose=True)
-        log(f"launch configuration: {cfg or 'library default'}")
-        mode_name = "adjoint GD" if wl.mode == W.GD_ADJ else "central-FD CD"
-        wall, kern, host = run_gpu(wl, args.steps, args.warmup, mode_name, cfg)
-        n_cert = int((host["cert"] == 1).sum())
-        flops = algorithmic_flops(wl, host["slot_fwd"], host["slot_bwd"])
-        kernel = "k_solve_gd" if wl.mode == W.GD_ADJ else "k_solve_cd"
-        config = {"workload": describe(wl), "points": wl.B, "guesses": wl.G, "n": wl.n,
-                  "nsteps": wl.nsteps, "certified_points": n_cert}
-    value = n_cert / wall
-    k_s = float(np.mean(kern)) / 1e3
-    achieved = flops / k_s / 1e12
+        rec, wall, host = measure_single(wl, args.workload, args.steps, args.warmup, cfg)
 
     result = {
         "metric": METRIC,
-        "value": value,
-        "unit": "certified solves/s",
+        "value": rec["value"],
+        "unit": rec["unit"],
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3,
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": rec["dtype"],
         "data": "synthetic",
-        "config": config,
-        "roofline": {
-            "bound": bound, "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": measured_traffic(args.workload, cfg),
-            "kernel": kernel, "launch": cfg, "kernel_ms": float(np.mean(kern)),
-            "algorithmic_flops_per_launch": flops,
-        },
+        "config": rec["config"],
+        "roofline": rec["roofline"],
     }
     # the central-FD comparison: the whole n=10 workload by default; for the
     # other workloads only on request (--cd-points), since coordinate descent
     # costs 3n solves per sweep
     want_cd = args.workload == "hopf_n10" or args.cd_points is not None
     if not batched and wl.mode == W.GD_ADJ and want_cd and not args.no_cd:
-        wcd = wl.with_(mode=W.CD_FD)
-        if args.cd_points:
-            wcd = wcd.subset(0, min(args.cd_points, wl.B))
-        cfg_cd = {} if args.no_tune else tune.tune(wcd, tune_iters=2, verbose=True)
-        log(f"launch configuration (CD): {cfg_cd or 'library default'}")
-        wall_cd, kern_cd, host_cd = run_gpu(wcd, 1, 0, "central-FD CD", cfg_cd)
-        m = wcd.B
-        fin = (host["cert"][:m] >= 0) & (host_cd["cert"] >= 0)
-        du = np.abs(host["u"][:m][fin] - host_cd["u"][fin]) / \
-            np.maximum(1, np.abs(host["u"][:m][fin]))
-        flops_cd = algorithmic_flops(wcd, host_cd["slot_fwd"], host_cd["slot_bwd"])
-        result["cd_fd"] = {
-            "points": m,
-            "ms_per_step": wall_cd * 1e3,
-            "certified_points": int((host_cd["cert"] == 1).sum()),
-            "value": int((host_cd["cert"] == 1).sum()) / wall_cd,
-            "achieved_tflops": flops_cd / (kern_cd[0] / 1e3) / 1e12,
-            "max_rel_u_diff_vs_adjoint": float(du.max(initial=0.0)),
-        }
-        # time per point of the two descents (equal when all points are run)
-        result["speedup_adjoint_vs_cd"] = (wall_cd / m) / (wall / wl.B)
+        result.update(cd_comparison(wl, host, wall, args.cd_points, not args.no_tune))
     if not args.no_cpu:
         log("CPU reference baseline ...")
-        result["cpu_baseline"] = cpu_baseline(wls)
+        if batched:
+            result["cpu_baseline"] = cpu_baseline_slots(wls, args.cpu_budget)
+        elif args.workload in ("hopf_n10", "lax_n32_drift"):
+            result["cpu_baseline"] = cpu_baseline_points(args.workload, args.cpu_budget,
+                                                         host_cores())
+        else:
+            result["cpu_baseline"] = cpu_baseline_slots(wls, args.cpu_budget)
         log(f"CPU: {result['cpu_baseline']['value']:.3f} certified solves/s")
+    # the metric's second dimension: the n=32 linear-drift workload (65536
+    # points, 8 guesses, 256 steps, checkpoint interval 16 as configured) in
+    # the same run, with its own matrix-core roofline, central-FD comparison
+    # on a prefix of the points and CPU baseline
+    if args.workload == "hopf_n10" and not args.no_n32:
+        w32 = W.c3_drift_n32()
+        cfg32 = {"ckpt_K": 16}
+        rec32, wall32, host32 = measure_single(w32, "lax_n32_drift", 2, 1, cfg32)
+        if not args.no_cd and args.n32_cd_points > 0:
+            rec32.update(cd_comparison(w32, host32, wall32, args.n32_cd_points, False))
+        if not args.no_cpu:
+            rec32["cpu_baseline"] = cpu_baseline_points("lax_n32_drift", args.cpu_budget,
+                                                        host_cores())
+            log(f"CPU n=32: {rec32['cpu_baseline']['value']:.3f} certified solves/s")
+        result["n32"] = rec32
     print(json.dumps(result), flush=True)
 
 
