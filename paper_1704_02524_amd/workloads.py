@@ -28,10 +28,13 @@ import numpy as np
 
 # enum values shared with the C interfaces (they are plain integers there)
 M_CONST, M_RAT, M_TANH = 0, 1, 2
-LAX, HOPF = 0, 1
+LAX, HOPF, LAX_MIN = 0, 1, 2          # functionals F1, G, F2 (grid minimum)
 TRAPZ, RK4AUG = 0, 1
-CD_FD, GD_ADJ = 0, 1
+CD_FD, GD_ADJ, ALG1, MOMENTUM = 0, 1, 2, 3
 F64, F32 = 0, 1
+RK4, EULER = 0, 1                     # characteristic ODE scheme
+H_QUADRATIC, H_NORM = 0, 1
+J_ELLIPSOID, J_ROSENBROCK = 0, 1
 
 SEED_BASE = 170402524
 
@@ -81,6 +84,24 @@ class Workload:
     # FP64 certificate rejects (the FP64 reference's attempt sequence)
     fp64_continue: bool = True
     seed: int = 0
+    # the paper's scheme and further families (section 4.1-4.2, section 5):
+    # ODE scheme, Hamiltonian and initial-data kinds, the degree-1 family's
+    # parameters (H = s1 c1(x)|p_A| + s2 c2(x)|p_B|, A = first k_split
+    # components, c_i = c0 (1 + beta exp(-gam |x -+ mu|^2))), the Rosenbrock
+    # scale, Algorithm 1's halving period M and the heavy-ball coefficient
+    ode: int = RK4
+    h_kind: int = H_QUADRATIC
+    j_kind: int = J_ELLIPSOID
+    k_split: int = 0
+    s1: float = 1.0
+    s2: float = 0.0
+    c0: float = 1.0
+    beta: float = 0.0
+    gam: float = 0.0
+    mu: Optional[np.ndarray] = None
+    rscale: float = 0.4e-3
+    M: int = 500
+    momentum: float = 0.9
 
     @property
     def B(self) -> int:
@@ -242,6 +263,89 @@ def c4_lax_n100(B: int = 262144, seed: int = SEED_BASE + 4) -> Workload:
         max_iter=300, alpha0=ALPHA_DEFAULT, eps_step=1e-6, cert_tol=1e-4, ckpt_K=8,
         cert_fp64=True, seed=seed)
     return _as_dtype(wl)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own experiments (section 5): a 2-D cross-section grid of query
+# points in [-3,3]^2 x {0}^(d-2), guesses U[-2,2]^d, the ellipse initial data
+# g(x) = 1/2(<x, A x> - 1) with A^-1 = diag(1, 25/4, 1/4, ..., 1/4) (semi-axes
+# a = (1, 5/2, 1/2, ...)), step Delta s, difference step sigma, 1/L, M = 500
+# and epsilon = 0.5e-7, forward Euler with the rectangle rule and Algorithm 1.
+# The paper does not state its grid; `grid` points per side.
+# ---------------------------------------------------------------------------
+def _paper_common(n, grid, G, seed, R_max=0):
+    g1 = np.linspace(-3.0, 3.0, grid)
+    xy = np.stack(np.meshgrid(g1, g1, indexing="ij"), axis=-1).reshape(-1, 2)
+    x = np.zeros((xy.shape[0], n))
+    x[:, :2] = xy
+    s_guess, = _streams(seed, 1)
+    guesses = s_guess.uniform(-2.0, 2.0, size=(x.shape[0], G, R_max + 1, n))
+    a = np.full(n, 0.5)
+    a[0] = 1.0
+    if n > 1:
+        a[1] = 2.5
+    return x, guesses, a
+
+
+def paper_ex2(sign: int = -1, n: int = 2, t: float = 0.5, grid: int = 64, G: int = 5,
+              seed: int = SEED_BASE + 5, cert_tol: float = 5e-2) -> Workload:
+    """Section 5 Example 2, the harmonic oscillator H = +-1/2(|p|^2 + |x|^2),
+    by the maximization (Hopf) principle: Delta s = 0.02, sigma = 0.001,
+    L = 3, 5 guesses per point."""
+    x, guesses, a = _paper_common(n, grid, G, seed)
+    return Workload(
+        name=f"paper_ex2_{'minus' if sign < 0 else 'plus'}_d{n}", n=n, t=t,
+        nsteps=int(round(t / 0.02)), m_kind=M_CONST, e=1, kappa=0.0, s=1.0, w=float(sign),
+        d=np.full(n, float(sign)), A=None, a=a, j0=-0.5, formula=HOPF, quad=TRAPZ, x=x,
+        guesses=guesses, mode=ALG1, dtype=F64, max_iter=20000, alpha0=1.0 / 3.0,
+        fd_sigma=1e-3, eps_step=0.5e-7, cert_tol=cert_tol, seed=seed, ode=EULER, M=500)
+
+
+def paper_ex2_rosenbrock(t: float = 0.5, grid: int = 64, G: int = 5,
+                         seed: int = SEED_BASE + 6, cert_tol: float = 5e-2) -> Workload:
+    """Section 5 Example 2 with the non-convex Rosenbrock initial data (eq.
+    weird) and the convex H+ = 1/2(|p|^2 + |x|^2), by the minimization (Lax)
+    principle, d = 2."""
+    wl = paper_ex2(sign=1, n=2, t=t, grid=grid, G=G, seed=seed, cert_tol=cert_tol)
+    return wl.with_(name="paper_ex2_rosenbrock", formula=LAX, j_kind=J_ROSENBROCK,
+                    rscale=0.4e-3)
+
+
+def paper_ex3(sign: int = 1, n: int = 2, t: float = 0.3, grid: int = 64, G: int = 5,
+              seed: int = SEED_BASE + 7, formula: int = LAX_MIN,
+              cert_tol: float = 5e-2) -> Workload:
+    """Section 5 Example 3, H = +-c(x)|p| with c(x) = 1 + 3 exp(-4|x -
+    (1,1,0,..)|^2), by the minimization (Lax) principle: Delta s = 0.02,
+    sigma = 0.001, L = 0.02; the grid-minimum functional F2 by default (the
+    integrand of F1 vanishes for degree-1 H)."""
+    x, guesses, a = _paper_common(n, grid, G, seed)
+    mu = np.zeros(n)
+    mu[:2] = 1.0
+    return Workload(
+        name=f"paper_ex3_{'plus' if sign > 0 else 'minus'}_d{n}", n=n, t=t,
+        nsteps=int(round(t / 0.02)), m_kind=M_CONST, e=1, kappa=0.0, s=1.0, w=0.0,
+        d=np.ones(n), A=None, a=a, j0=-0.5, formula=formula, quad=TRAPZ, x=x,
+        guesses=guesses, mode=ALG1, dtype=F64, max_iter=20000, alpha0=1.0 / 0.02,
+        fd_sigma=1e-3, eps_step=0.5e-7, cert_tol=cert_tol, seed=seed, ode=EULER, M=500,
+        h_kind=H_NORM, k_split=n, s1=float(sign), s2=0.0, c0=1.0, beta=3.0, gam=4.0, mu=mu)
+
+
+def paper_ex5(n: int = 2, t: float = 0.3, grid: int = 64, G: int = 20,
+              seed: int = SEED_BASE + 8, cert_tol: float = 5e-2) -> Workload:
+    """Section 5 Example 5, H = c1(x)|p_1| - c2(x)|p_2..d| with c1(x) = c(x),
+    c2(x) = c(-x), c(x) = 2(1 + 3 exp(-4|x - (1,1,0,..)|^2)), by the
+    maximization (Hopf) principle: Delta s = 0.02, sigma = 0.001, L = 50,
+    20 guesses per point."""
+    x, guesses, a = _paper_common(n, grid, G, seed)
+    mu = np.zeros(n)
+    mu[:2] = 1.0
+    return Workload(
+        name=f"paper_ex5_d{n}", n=n, t=t, nsteps=int(round(t / 0.02)), m_kind=M_CONST, e=1,
+        kappa=0.0, s=1.0, w=0.0, d=np.ones(n), A=None, a=a, j0=-0.5, formula=HOPF,
+        quad=TRAPZ, x=x, guesses=guesses, mode=ALG1, dtype=F64, max_iter=20000,
+        alpha0=1.0 / 50.0, fd_sigma=1e-3, eps_step=0.5e-7, cert_tol=cert_tol, seed=seed,
+        ode=EULER, M=500, h_kind=H_NORM, k_split=1, s1=1.0, s2=-1.0, c0=2.0, beta=3.0,
+        gam=4.0, mu=mu)
 
 
 def _as_dtype(wl: Workload) -> Workload:
