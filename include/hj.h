@@ -71,13 +71,34 @@ extern "C" {
 #define HJ_MAX_N   128      /* space dimension                              */
 #define HJ_MAX_N_DRIFT 64   /* space dimension with a drift matrix A        */
 
-enum { HJ_H_QUADRATIC = 0 };              /* H_kind: the family above       */
-enum { HJ_J_ELLIPSOID = 0 };              /* J_kind: ellipsoid g            */
+/* H_kind: the quadratic family above, or the degree-1 homogeneous family
+ * of section 5 Examples 3 and 5,
+ *     H(x, p) = s1 c1(x) |p_A| + s2 c2(x) |p_B|,  A = {1..k}, B = {k+1..n},
+ *     c1(x) = c0 (1 + beta exp(-gam |x - mu|^2)), c2(x) = c1(-x) with the
+ *     same constants (the zero subgradient where p_A or p_B vanishes). */
+enum { HJ_H_QUADRATIC = 0, HJ_H_NORM = 1 };
+/* J_kind: the ellipsoid g above, or the Rosenbrock initial data of section 5
+ * Example 2 (eq. weird), n = 2 and Lax functionals only:
+ *     g(x) = rscale (-100 + (1 - x_1)^2 + 100 (1 + x_2 - x_1^2)^2). */
+enum { HJ_J_ELLIPSOID = 0, HJ_J_ROSENBROCK = 1 };
 enum { HJ_M_CONST = 0, HJ_M_RAT = 1, HJ_M_TANH = 2 };
-enum { HJ_LAX = 0, HJ_HOPF = 1 };
+/* formula: the Lax functional F1, the Hopf functional G, or the grid-minimum
+ * functional F2(v) = min_k g(gamma_k) over the characteristic's nodes
+ * (section 4.1, eq. num_min; minimised, phi = min F2) */
+enum { HJ_LAX = 0, HJ_HOPF = 1, HJ_LAX_MIN = 2 };
 enum { HJ_TRAPZ = 0, HJ_RK4AUG = 1 };     /* trapezoid on the RK4 nodes, or
                                              RK4 applied to a' = integrand */
-enum { HJ_CD_FD = 0, HJ_GD_ADJ = 1 };
+/* descent: central-difference coordinate descent with step halving on
+ * insufficient decrease, adjoint gradient descent, Algorithm 1 of section
+ * 4.1 read literally (forward differences, eq. num_diff; no acceptance test;
+ * alpha halved every M coordinate updates; stop after n consecutive moves
+ * below eps_step), or heavy-ball descent on forward differences
+ * (v' = v - alpha g + momentum (v - v_prev), a rising trial rejected with
+ * the momentum dropped and alpha halved) */
+enum { HJ_CD_FD = 0, HJ_GD_ADJ = 1, HJ_ALG1 = 2, HJ_MOMENTUM = 3 };
+/* characteristic ODE: classical RK4, or forward Euler with the rectangle
+ * rule h sum_{k<N} integrand(y_k) (section 4.2, eq. num_int) */
+enum { HJ_RK4 = 0, HJ_EULER = 1 };
 enum { HJ_F64 = 0, HJ_F32 = 1 };
 /* stop status of one descent run */
 enum { HJ_ST_MAXITER = 0, HJ_ST_CONVERGED = 1, HJ_ST_STALLED = 2, HJ_ST_DIVERGED = 3 };
@@ -93,11 +114,18 @@ typedef struct {
                              With A the kernels run on the matrix cores:
                              n <= HJ_MAX_N_DRIFT, 4 lanes per task, not in
                              batched plans (HJ_EUNSUPPORTED otherwise)     */
+    /* HJ_H_NORM only (d, m_kind, e, kappa, s, w and A are then unused)    */
+    int32_t k;            /* size of block A, 0..n                         */
+    double  s1, s2;       /* signs (or weights) of the two blocks          */
+    double  c0, beta, gam;
+    const double *mu;     /* host [n] centre of the bump                   */
 } hj_h_params;
 
 typedef struct {
-    const double *a;      /* host [n] ellipsoid semi-axes, nonzero         */
+    const double *a;      /* host [n] ellipsoid semi-axes, nonzero (may be
+                             NULL for HJ_J_ROSENBROCK)                      */
     double j0;
+    double rscale;        /* HJ_J_ROSENBROCK: the factor r                 */
 } hj_j_params;
 
 typedef struct {
@@ -149,6 +177,9 @@ typedef struct {
                              restarts from its remaining guesses -- in a
                              second launch over the handed-off slots only.
                              0: the FP32 attempts alone decide.            */
+    int32_t ode;          /* HJ_RK4 or HJ_EULER                            */
+    int32_t M;            /* HJ_ALG1: alpha halves every M updates (>= 1)  */
+    double  momentum;     /* HJ_MOMENTUM: the heavy-ball coefficient       */
 } hj_opts;
 
 enum {
@@ -172,6 +203,13 @@ typedef struct {
     int64_t *n_bwd;       /* adjoint sweeps over all attempts              */
     void    *v_final;     /* the reported attempt's v                      */
 } hj_slot_diag;
+
+/* The paper's scheme and families run in a kernel of their own: a solve
+ * with mode HJ_ALG1 or HJ_MOMENTUM (the only modes for HJ_H_NORM,
+ * HJ_J_ROSENBROCK, HJ_LAX_MIN or HJ_EULER) takes FP64, no drift matrix,
+ * n <= 16, one lane per (point, guess) (lanes_per_task and the schedule are
+ * ignored) and the RK4-augmented rule with HJ_RK4; other combinations are
+ * HJ_EUNSUPPORTED.  hj_eval evaluates these functionals without gradients. */
 
 /* hj_solve -- phi(x_b, t) for B query points (sections 3.3-3.4, Algorithm 1,
  * certificate of section 4.3, multiple guesses of section 5).

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libhj.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = (["hj_api.hip"] + [f"hj_inst_{t}_{i}.hip" for t in ("f64", "f32") for i in range(5)]
-           + [f"hj_inst_c64_{i}.hip" for i in range(4)])
+           + [f"hj_inst_c64_{i}.hip" for i in range(4)] + ["hj_inst_paper.hip"])
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

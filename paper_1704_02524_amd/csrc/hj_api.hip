@@ -271,23 +271,43 @@ int get_workspace(const hj_opts* o, size_t need, void** out) {
 
 int check_problem(int H_kind, const hj_h_params* H, int J_kind, const hj_j_params* J, int n,
                   double t, int nsteps) {
-  if (H_kind != HJ_H_QUADRATIC) return fail(HJ_EUNSUPPORTED, "unknown H_kind");
-  if (J_kind != HJ_J_ELLIPSOID) return fail(HJ_EUNSUPPORTED, "unknown J_kind");
+  if (H_kind != HJ_H_QUADRATIC && H_kind != HJ_H_NORM)
+    return fail(HJ_EUNSUPPORTED, "unknown H_kind");
+  if (J_kind != HJ_J_ELLIPSOID && J_kind != HJ_J_ROSENBROCK)
+    return fail(HJ_EUNSUPPORTED, "unknown J_kind");
   if (!H || !J) return fail(HJ_EINVAL, "H and J parameters are required");
   if (n < 1) return fail(HJ_EINVAL, "n must be >= 1");
   if (n > HJ_MAX_N) return fail(HJ_EUNSUPPORTED, "n above HJ_MAX_N");
   if (!(t > 0.0) || !std::isfinite(t)) return fail(HJ_EINVAL, "t must be finite and > 0");
   if (nsteps < 1) return fail(HJ_EINVAL, "nsteps must be >= 1");
-  if (H->m_kind < HJ_M_CONST || H->m_kind > HJ_M_TANH) return fail(HJ_EINVAL, "bad m_kind");
-  if (H->e != 1 && H->e != 2) return fail(HJ_EINVAL, "e must be 1 or 2");
-  if (H->m_kind == HJ_M_TANH && !(H->s > 0.0)) return fail(HJ_EINVAL, "tanh scale s must be > 0");
-  if (!H->d || !J->a) return fail(HJ_EINVAL, "d and a arrays are required");
-  if (H->A)
-    for (int i = 0; i < n * n; ++i)
-      if (!std::isfinite(H->A[i])) return fail(HJ_EINVAL, "drift matrix entries must be finite");
-  for (int i = 0; i < n; ++i)
-    if (!(J->a[i] != 0.0) || !std::isfinite(J->a[i]))
-      return fail(HJ_EINVAL, "ellipsoid axes must be finite and nonzero");
+  if (H_kind == HJ_H_QUADRATIC) {
+    if (H->m_kind < HJ_M_CONST || H->m_kind > HJ_M_TANH) return fail(HJ_EINVAL, "bad m_kind");
+    if (H->e != 1 && H->e != 2) return fail(HJ_EINVAL, "e must be 1 or 2");
+    if (H->m_kind == HJ_M_TANH && !(H->s > 0.0))
+      return fail(HJ_EINVAL, "tanh scale s must be > 0");
+    if (!H->d) return fail(HJ_EINVAL, "the weights d are required");
+    if (H->A)
+      for (int i = 0; i < n * n; ++i)
+        if (!std::isfinite(H->A[i]))
+          return fail(HJ_EINVAL, "drift matrix entries must be finite");
+  } else {
+    if (!H->mu) return fail(HJ_EINVAL, "the centre mu is required");
+    if (H->k < 0 || H->k > n) return fail(HJ_EINVAL, "block size k must be in [0, n]");
+    if (!std::isfinite(H->s1) || !std::isfinite(H->s2) || !std::isfinite(H->c0) ||
+        !std::isfinite(H->beta) || !(H->gam >= 0.0) || !std::isfinite(H->gam))
+      return fail(HJ_EINVAL, "s1, s2, c0, beta must be finite and gam >= 0");
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(H->mu[i])) return fail(HJ_EINVAL, "mu must be finite");
+  }
+  if (J_kind == HJ_J_ROSENBROCK) {
+    if (n != 2) return fail(HJ_EUNSUPPORTED, "the Rosenbrock initial data take n = 2");
+    if (!std::isfinite(J->rscale)) return fail(HJ_EINVAL, "rscale must be finite");
+  } else {
+    if (!J->a) return fail(HJ_EINVAL, "the ellipsoid axes a are required");
+    for (int i = 0; i < n; ++i)
+      if (!(J->a[i] != 0.0) || !std::isfinite(J->a[i]))
+        return fail(HJ_EINVAL, "ellipsoid axes must be finite and nonzero");
+  }
   return HJ_OK;
 }
 
@@ -726,13 +746,22 @@ hj_opts default_opts() {
   o.acc_rel = 64 * 2.220446049250313e-16;
   o.armijo_c = 0.1;
   o.fp64_continue = 1;
+  o.ode = HJ_RK4;
+  o.M = 500;
+  o.momentum = 0.9;
   return o;
 }
 
 int check_opts(const hj_opts* o) {
   if (o->dtype != HJ_F64 && o->dtype != HJ_F32) return fail(HJ_EDTYPE, "unknown dtype");
-  if (o->formula != HJ_LAX && o->formula != HJ_HOPF) return fail(HJ_EINVAL, "bad formula");
-  if (o->mode != HJ_CD_FD && o->mode != HJ_GD_ADJ) return fail(HJ_EINVAL, "bad mode");
+  if (o->formula < HJ_LAX || o->formula > HJ_LAX_MIN) return fail(HJ_EINVAL, "bad formula");
+  if (o->mode < HJ_CD_FD || o->mode > HJ_MOMENTUM) return fail(HJ_EINVAL, "bad mode");
+  if (o->ode != HJ_RK4 && o->ode != HJ_EULER) return fail(HJ_EINVAL, "bad ode scheme");
+  if (o->mode == HJ_ALG1 && o->M < 1) return fail(HJ_EINVAL, "M must be >= 1");
+  if ((o->mode == HJ_ALG1 || o->mode == HJ_MOMENTUM) && !(o->fd_sigma > 0.0))
+    return fail(HJ_EINVAL, "fd_sigma must be > 0");
+  if (o->mode == HJ_MOMENTUM && !(o->momentum >= 0.0 && o->momentum < 1.0))
+    return fail(HJ_EINVAL, "momentum must be in [0, 1)");
   if (o->quad != HJ_TRAPZ && o->quad != HJ_RK4AUG) return fail(HJ_EINVAL, "bad quadrature");
   if (o->max_iter < 0) return fail(HJ_EINVAL, "max_iter must be >= 0");
   if (o->ckpt_K < 1) return fail(HJ_EINVAL, "ckpt_K must be >= 1");
@@ -744,6 +773,150 @@ int check_opts(const hj_opts* o) {
   if (o->schedule < HJ_SCHED_AUTO || o->schedule > HJ_SCHED_PERSISTENT)
     return fail(HJ_EINVAL, "bad schedule");
   if (o->max_groups < 0) return fail(HJ_EINVAL, "max_groups must be >= 0");
+  return HJ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the paper's scheme and families (hj_paper.hpp)
+// ---------------------------------------------------------------------------
+bool needs_paper(int H_kind, int J_kind, const hj_opts* o) {
+  return o->mode == HJ_ALG1 || o->mode == HJ_MOMENTUM || H_kind == HJ_H_NORM ||
+         J_kind == HJ_J_ROSENBROCK || o->formula == HJ_LAX_MIN || o->ode == HJ_EULER;
+}
+
+int check_paper(int H_kind, const hj_h_params* H, int J_kind, int n, const hj_opts* o,
+                bool solve) {
+  if (solve && o->mode != HJ_ALG1 && o->mode != HJ_MOMENTUM)
+    return fail(HJ_EUNSUPPORTED, "these Hamiltonians, initial data, functionals and the "
+                                 "Euler scheme descend with HJ_ALG1 or HJ_MOMENTUM");
+  if (o->dtype != HJ_F64) return fail(HJ_EUNSUPPORTED, "the paper's scheme runs in FP64");
+  if (H_kind == HJ_H_QUADRATIC && H->A)
+    return fail(HJ_EUNSUPPORTED, "the paper's scheme takes no drift matrix");
+  if (n > hj::kPaperMaxN)
+    return fail(HJ_EUNSUPPORTED, "the paper's scheme takes n <= " +
+                                     std::to_string(hj::kPaperMaxN));
+  if (J_kind == HJ_J_ROSENBROCK && o->formula == HJ_HOPF)
+    return fail(HJ_EUNSUPPORTED, "the Hopf functional needs the ellipsoid's conjugate");
+  if (o->ode == HJ_RK4 && o->quad != HJ_RK4AUG)
+    return fail(HJ_EUNSUPPORTED, "the paper's kernel pairs RK4 with the RK4-augmented rule");
+  return HJ_OK;
+}
+
+hj::PaperProblem paper_problem(int H_kind, const hj_h_params* H, int J_kind,
+                               const hj_j_params* J, int n, double t, int nsteps,
+                               const hj_opts* o) {
+  hj::PaperProblem P;
+  std::memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.hkind = H_kind;
+  P.jkind = J_kind;
+  P.functional = o->formula;
+  P.ode = o->ode;
+  P.N = nsteps;
+  P.h = t / nsteps;
+  if (H_kind == HJ_H_QUADRATIC) {
+    P.m_kind = H->m_kind;
+    P.e = H->e;
+    P.kappa = H->m_kind == HJ_M_CONST ? 0.0 : H->kappa;
+    P.inv_s = H->m_kind == HJ_M_TANH ? 1.0 / H->s : 1.0;
+    P.w = H->w;
+    for (int i = 0; i < n; ++i) P.d[i] = H->d[i];
+  } else {
+    P.k = H->k;
+    P.s1 = H->s1;
+    P.s2 = H->s2;
+    P.c0 = H->c0;
+    P.beta = H->beta;
+    P.gam = H->gam;
+    for (int i = 0; i < n; ++i) P.mu[i] = H->mu[i];
+  }
+  for (int i = 0; i < hj::kPaperMaxN; ++i) {
+    P.a2[i] = 1.0;
+    P.ia2[i] = 1.0;
+  }
+  if (J_kind == HJ_J_ELLIPSOID)
+    for (int i = 0; i < n; ++i) {
+      P.a2[i] = J->a[i] * J->a[i];
+      P.ia2[i] = 1.0 / (J->a[i] * J->a[i]);
+    }
+  P.j0 = J->j0;
+  P.rscale = J->rscale;
+  return P;
+}
+
+int paper_solve(int H_kind, const hj_h_params* H, int J_kind, const hj_j_params* J,
+                const void* x, int64_t B, int n, double t, int nsteps, const hj_guesses* gs,
+                const hj_opts* o, double* out_u, void* out_argopt, int32_t* out_cert,
+                const hj_slot_diag* diag) {
+  int rc = check_paper(H_kind, H, J_kind, n, o, true);
+  if (rc) return rc;
+  const size_t BG = (size_t)B * gs->G;
+  const size_t need = align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * n * 8, 256);
+  void* ws = nullptr;
+  rc = get_workspace(o, need, &ws);
+  if (rc) return rc;
+  char* sp = static_cast<char*>(ws);
+  hj::PaperArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.P = paper_problem(H_kind, H, J_kind, J, n, t, nsteps, o);
+  A.mode = o->mode;
+  A.max_iter = o->max_iter;
+  A.R = gs->R_max;
+  A.G = gs->G;
+  A.M = o->M;
+  A.alpha0 = o->alpha0;
+  A.sigma = o->fd_sigma;
+  A.eps = o->eps_step;
+  A.cert_tol = o->cert_tol;
+  A.v_max = o->v_max;
+  A.momentum = o->momentum;
+  A.acc_rel = o->acc_rel;
+  A.x = static_cast<const double*>(x);
+  A.guesses = static_cast<const double*>(gs->init);
+  A.ntask = (int64_t)BG;
+  double* w_phi = reinterpret_cast<double*>(sp);
+  double* w_rho = w_phi + BG;
+  int32_t* w_status = reinterpret_cast<int32_t*>(w_rho + BG);
+  int32_t* w_cert = w_status + BG;
+  int32_t* w_iters = w_cert + BG;
+  int32_t* w_att = w_iters + BG;
+  int64_t* w_fwd = reinterpret_cast<int64_t*>(w_att + BG);
+  int64_t* w_bwd = w_fwd + BG;
+  double* w_v = reinterpret_cast<double*>(sp + align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256));
+  A.out.phi = (diag && diag->phi) ? diag->phi : w_phi;
+  A.out.rho = (diag && diag->rho) ? diag->rho : w_rho;
+  A.out.status = (diag && diag->status) ? diag->status : w_status;
+  A.out.cert = (diag && diag->cert) ? diag->cert : w_cert;
+  A.out.iters = (diag && diag->iters) ? diag->iters : w_iters;
+  A.out.attempts = (diag && diag->attempts) ? diag->attempts : w_att;
+  A.out.n_fwd = (diag && diag->n_fwd) ? diag->n_fwd : w_fwd;
+  A.out.n_bwd = (diag && diag->n_bwd) ? diag->n_bwd : w_bwd;
+  A.out.v = (diag && diag->v_final) ? static_cast<double*>(diag->v_final) : w_v;
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
+  HJ_HIP(hj::launch_solve_paper(A, st));
+  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
+  // selection over the guesses (u = min F1 / F2, or -min G)
+  HJ_HIP(hj::launch_select<double>(B, gs->G, n, o->formula == HJ_HOPF ? HJ_HOPF : HJ_LAX,
+                                   A.out.phi, A.out.cert, A.out.v, out_u,
+                                   static_cast<double*>(out_argopt), out_cert, st));
+  return HJ_OK;
+}
+
+int paper_eval(int H_kind, const hj_h_params* H, int J_kind, const hj_j_params* J,
+               const void* x, int64_t B, int n, double t, int nsteps, const void* v, int G,
+               const hj_opts* o, double* out_phi, void* out_yN, double* out_rho,
+               void* out_gv, void* out_gx) {
+  int rc = check_paper(H_kind, H, J_kind, n, o, false);
+  if (rc) return rc;
+  if (out_gv || out_gx || out_yN)
+    return fail(HJ_EUNSUPPORTED, "the paper's scheme evaluates objectives and residuals only");
+  hipStream_t st = static_cast<hipStream_t>(o->stream);
+  const hj::PaperProblem P = paper_problem(H_kind, H, J_kind, J, n, t, nsteps, o);
+  if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
+  HJ_HIP(hj::launch_eval_paper(P, static_cast<const double*>(x), static_cast<const double*>(v),
+                               B, G, out_phi, out_rho, st));
+  if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
   return HJ_OK;
 }
 
@@ -1045,6 +1218,9 @@ int32_t hj_solve(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_
   if (B == 0) return HJ_OK;
   if (!x || !guesses->init || !out_u || !out_argopt || !out_cert)
     return fail(HJ_EINVAL, "x, guesses->init and the outputs are required");
+  if (needs_paper(H_kind, J_kind, &o))
+    return paper_solve(H_kind, H, J_kind, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt,
+                       out_cert, diag);
   if (o.dtype == HJ_F64)
     return solve_t<double>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert,
                            diag);
@@ -1072,6 +1248,21 @@ int32_t hj_solve_noalloc(int32_t H_kind, const hj_h_params* H, int32_t J_kind,
   if (B == 0) return HJ_OK;
   if (!x || !guesses->init || !out_u || !out_argopt || !out_cert)
     return fail(HJ_EINVAL, "x, guesses->init and the outputs are required");
+  if (needs_paper(H_kind, J_kind, &o)) {
+    const size_t BG = (size_t)B * guesses->G;
+    const size_t need = align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * n * 8, 256);
+    if (need > HJ_NOALLOC_BYTES)
+      return fail(HJ_ENOMEM, "hj_solve_noalloc: this solve needs " + std::to_string(need) +
+                                 " bytes of scratch; the fixed scratch holds " +
+                                 std::to_string((size_t)HJ_NOALLOC_BYTES) + " bytes");
+    void* ptr = nullptr;
+    rc = noalloc_scratch(&ptr);
+    if (rc) return rc;
+    o.workspace = ptr;
+    o.ws_bytes = HJ_NOALLOC_BYTES;
+    return paper_solve(H_kind, H, J_kind, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt,
+                       out_cert, diag);
+  }
   Shape s{};
   rc = shape_for(H, n, o.lanes_per_task, o.dtype == HJ_F32, s);
   if (rc) return rc;
@@ -1131,6 +1322,9 @@ int32_t hj_eval(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j
   if (rc) return rc;
   if (B == 0) return HJ_OK;
   if (!x || !v || !out_phi) return fail(HJ_EINVAL, "x, v and out_phi are required");
+  if (needs_paper(H_kind, J_kind, &o))
+    return paper_eval(H_kind, H, J_kind, J, x, B, n, t, nsteps, v, G, &o, out_phi, out_yN,
+                      out_rho, out_grad_v, out_grad_x);
   if (o.dtype == HJ_F64)
     return eval_t<double>(H, J, x, B, n, t, nsteps, v, G, &o, out_phi, out_yN, out_rho,
                           out_grad_v, out_grad_x);
@@ -1171,6 +1365,9 @@ int32_t hj_batch_plan(int32_t H_kind, int32_t J_kind, const hj_instance* inst, i
   int rc = check_opts(&o);
   if (rc) return rc;
   if (o.mode != HJ_GD_ADJ) return fail(HJ_EUNSUPPORTED, "batched solves use HJ_GD_ADJ");
+  if (needs_paper(H_kind, J_kind, &o))
+    return fail(HJ_EUNSUPPORTED, "batched plans take the quadratic family, ellipsoid data, "
+                                 "the F1 / G functionals and RK4");
   for (int i = 0; i < n_inst; ++i) {
     const hj_instance& I = inst[i];
     rc = check_problem(H_kind, &I.H, J_kind, &I.J, I.n, I.t, I.nsteps);

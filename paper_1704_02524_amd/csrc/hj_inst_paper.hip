@@ -1,0 +1,54 @@
+// Kernel instances and launchers of the paper's scheme and families: one
+// lane per (point, guess) task, 2, 4, 8 or 16 components per lane, both
+// Hamiltonian families.
+#include "hj_paper.hpp"
+
+namespace hj {
+
+namespace {
+template <int NPL> hipError_t solve_npl(const PaperArgs& A, hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (A.ntask + block - 1) / block;
+  if (A.P.hkind == HJ_H_NORM)
+    hipLaunchKernelGGL((k_solve_paper<NPL, HJ_H_NORM>), dim3((unsigned)grid), dim3(block), 0,
+                       st, A);
+  else
+    hipLaunchKernelGGL((k_solve_paper<NPL, HJ_H_QUADRATIC>), dim3((unsigned)grid), dim3(block),
+                       0, st, A);
+  return hipGetLastError();
+}
+template <int NPL>
+hipError_t eval_npl(const PaperProblem& P, const double* x, const double* v, int64_t B, int G,
+                    double* phi, double* rho, hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (B * G + block - 1) / block;
+  if (P.hkind == HJ_H_NORM)
+    hipLaunchKernelGGL((k_eval_paper<NPL, HJ_H_NORM>), dim3((unsigned)grid), dim3(block), 0, st,
+                       P, x, v, B, G, phi, rho);
+  else
+    hipLaunchKernelGGL((k_eval_paper<NPL, HJ_H_QUADRATIC>), dim3((unsigned)grid), dim3(block), 0,
+                       st, P, x, v, B, G, phi, rho);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_solve_paper(const PaperArgs& A, hipStream_t st) {
+  const int n = A.P.n;
+  if (n <= 2) return solve_npl<2>(A, st);
+  if (n <= 4) return solve_npl<4>(A, st);
+  if (n <= 8) return solve_npl<8>(A, st);
+  if (n <= kPaperMaxN) return solve_npl<16>(A, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_eval_paper(const PaperProblem& P, const double* x, const double* v, int64_t B,
+                             int G, double* phi, double* rho, hipStream_t st) {
+  const int n = P.n;
+  if (n <= 2) return eval_npl<2>(P, x, v, B, G, phi, rho, st);
+  if (n <= 4) return eval_npl<4>(P, x, v, B, G, phi, rho, st);
+  if (n <= 8) return eval_npl<8>(P, x, v, B, G, phi, rho, st);
+  if (n <= kPaperMaxN) return eval_npl<16>(P, x, v, B, G, phi, rho, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace hj

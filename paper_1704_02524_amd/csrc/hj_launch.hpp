@@ -97,6 +97,32 @@ template <typename T> struct EvalArgs {
   size_t stride;
 };
 
+// The paper's scheme and families (hj_paper.hpp): the problem by value, n <=
+// kPaperMaxN, padded components zero.
+constexpr int kPaperMaxN = 16;
+
+struct PaperProblem {
+  int n, hkind, jkind, functional, ode, N, m_kind, e, k;
+  double h, kappa, inv_s, w, s1, s2, c0, beta, gam, j0, rscale;
+  double d[kPaperMaxN], a2[kPaperMaxN], ia2[kPaperMaxN], mu[kPaperMaxN];
+};
+
+struct PaperArgs {
+  PaperProblem P;
+  int mode, max_iter, R, G, M;
+  double alpha0, sigma, eps, cert_tol, v_max, momentum, acc_rel;
+  const double* x;        // [B, n]
+  const double* guesses;  // [B, G, R+1, n]
+  int64_t ntask;
+  SlotOut<double> out;    // per-slot records [B * G]
+};
+
+// One lane per task over A.ntask tasks (hj_inst_paper.hip).
+hipError_t launch_solve_paper(const PaperArgs& A, hipStream_t st);
+// The functional at v [B, G, n]: phi and rho [B, G].
+hipError_t launch_eval_paper(const PaperProblem& P, const double* x, const double* v, int64_t B,
+                             int G, double* phi, double* rho, hipStream_t st);
+
 // Launch a descent kernel over A.ntask tasks.  grid_groups = 0: one task
 // group per task (no queue); otherwise a persistent launch of grid_groups
 // task groups fed by A.queue (reset by this call with a small kernel, so the

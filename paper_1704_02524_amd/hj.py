@@ -27,11 +27,13 @@ _dp = C.POINTER(C.c_double)
 
 class HParams(C.Structure):
     _fields_ = [("m_kind", C.c_int32), ("e", C.c_int32), ("kappa", C.c_double),
-                ("s", C.c_double), ("w", C.c_double), ("d", _dp), ("A", _dp)]
+                ("s", C.c_double), ("w", C.c_double), ("d", _dp), ("A", _dp),
+                ("k", C.c_int32), ("s1", C.c_double), ("s2", C.c_double), ("c0", C.c_double),
+                ("beta", C.c_double), ("gam", C.c_double), ("mu", _dp)]
 
 
 class JParams(C.Structure):
-    _fields_ = [("a", _dp), ("j0", C.c_double)]
+    _fields_ = [("a", _dp), ("j0", C.c_double), ("rscale", C.c_double)]
 
 
 class Guesses(C.Structure):
@@ -47,7 +49,8 @@ class Opts(C.Structure):
                 ("armijo_c", C.c_double),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("schedule", C.c_int32),
-                ("max_groups", C.c_int32), ("fp64_continue", C.c_int32)]
+                ("max_groups", C.c_int32), ("fp64_continue", C.c_int32),
+                ("ode", C.c_int32), ("M", C.c_int32), ("momentum", C.c_double)]
 
 SCHED_AUTO, SCHED_STATIC, SCHED_PERSISTENT = 0, 1, 2
 
@@ -135,10 +138,15 @@ class Problem:
         self._d = np.ascontiguousarray(wl.d, dtype=np.float64)
         self._a = np.ascontiguousarray(wl.a, dtype=np.float64)
         self._A = None if wl.A is None else np.ascontiguousarray(wl.A, dtype=np.float64)
+        self._mu = np.ascontiguousarray(wl.mu if wl.mu is not None else np.zeros(wl.n),
+                                        dtype=np.float64)
+        self.h_kind, self.j_kind = wl.h_kind, wl.j_kind
         self.H = HParams(wl.m_kind, wl.e, wl.kappa, wl.s, wl.w,
                          self._d.ctypes.data_as(_dp),
-                         None if self._A is None else self._A.ctypes.data_as(_dp))
-        self.J = JParams(self._a.ctypes.data_as(_dp), wl.j0)
+                         None if self._A is None else self._A.ctypes.data_as(_dp),
+                         wl.k_split, wl.s1, wl.s2, wl.c0, wl.beta, wl.gam,
+                         self._mu.ctypes.data_as(_dp))
+        self.J = JParams(self._a.ctypes.data_as(_dp), wl.j0, wl.rscale)
 
 
 def make_opts(wl, stream: Optional[torch.cuda.Stream] = None, events=None, **over) -> Opts:
@@ -148,7 +156,8 @@ def make_opts(wl, stream: Optional[torch.cuda.Stream] = None, events=None, **ove
               max_iter=wl.max_iter, ckpt_K=wl.ckpt_K, cert_fp64=int(wl.cert_fp64),
               alpha0=wl.alpha0, fd_sigma=wl.fd_sigma, eps_step=wl.eps_step,
               cert_tol=wl.cert_tol, v_max=wl.v_max, acc_rel=wl.acc_rel,
-              armijo_c=wl.armijo_c, fp64_continue=int(wl.fp64_continue))
+              armijo_c=wl.armijo_c, fp64_continue=int(wl.fp64_continue), ode=wl.ode,
+              M=wl.M, momentum=wl.momentum)
     kw.update(over)
     o = Opts()
     for k, v in kw.items():
@@ -209,7 +218,7 @@ def solve(wl, x: torch.Tensor, guesses: torch.Tensor, diag: bool = True,
                      _ptr(out["slot_v"]))
     gs = Guesses(G, R1 - 1, _ptr(guesses))
     fn = lib().hj_solve_noalloc if noalloc else lib().hj_solve
-    rc = fn(HJ_H_QUADRATIC, C.byref(prob.H), HJ_J_ELLIPSOID, C.byref(prob.J),
+    rc = fn(prob.h_kind, C.byref(prob.H), prob.j_kind, C.byref(prob.J),
             _ptr(x), B, n, float(wl.t), int(wl.nsteps), C.byref(gs), C.byref(o),
             _ptr(out["u"]), _ptr(out["argopt"]), _ptr(out["cert"]),
             C.byref(D) if D is not None else None)
@@ -236,7 +245,7 @@ def evaluate(wl, x: torch.Tensor, v: torch.Tensor, grad: bool = False, yN: bool 
     if grad:
         out["grad_v"] = torch.empty(B, G, n, dtype=dt, device=dev)
         out["grad_x"] = torch.empty(B, G, n, dtype=dt, device=dev)
-    rc = lib().hj_eval(HJ_H_QUADRATIC, C.byref(prob.H), HJ_J_ELLIPSOID, C.byref(prob.J),
+    rc = lib().hj_eval(prob.h_kind, C.byref(prob.H), prob.j_kind, C.byref(prob.J),
                        _ptr(x), B, n, float(wl.t), int(wl.nsteps), _ptr(v), G, C.byref(o),
                        _ptr(out["phi"]), _ptr(out.get("yN")), _ptr(out["rho"]),
                        _ptr(out.get("grad_v")), _ptr(out.get("grad_x")))
@@ -246,23 +255,27 @@ def evaluate(wl, x: torch.Tensor, v: torch.Tensor, grad: bool = False, yN: bool 
 
 class HJFunctional(torch.autograd.Function):
     """The discretised Lax / Hopf objective as a differentiable function of
-    (x, v): forward is the RK4 solve with quadrature, backward the discrete
-    adjoint, both in libhj.so.  x [B, n], v [B, G, n] -> phi [B, G] (float64)."""
+    (x, v): x [B, n], v [B, G, n] -> phi [B, G] (float64), both directions in
+    libhj.so.  When a gradient can be asked for, the forward runs the RK4
+    solve with checkpoints and the discrete adjoint in one kernel (hj_eval
+    with gradients) and keeps d phi / d v and d phi / d x, so the backward
+    only scales them by the incoming gradient: one forward solve and one
+    adjoint sweep per step, never a second forward solve."""
 
     @staticmethod
     def forward(ctx, x, v, wl):
-        out = evaluate(wl, x.contiguous(), v.contiguous(), grad=False)
-        ctx.save_for_backward(x, v)
-        ctx.wl = wl
+        need = torch.is_grad_enabled() and (x.requires_grad or v.requires_grad)
+        out = evaluate(wl, x.detach().contiguous(), v.detach().contiguous(), grad=need)
+        if need:
+            ctx.save_for_backward(out["grad_x"], out["grad_v"])
         return out["phi"]
 
     @staticmethod
     def backward(ctx, gphi):
-        x, v = ctx.saved_tensors
-        out = evaluate(ctx.wl, x.contiguous(), v.contiguous(), grad=True)
-        g = gphi.to(out["grad_v"].dtype)
-        gv = out["grad_v"] * g.unsqueeze(-1)
-        gx = (out["grad_x"] * g.unsqueeze(-1)).sum(dim=1)
+        gx_all, gv_all = ctx.saved_tensors
+        g = gphi.to(gv_all.dtype).unsqueeze(-1)
+        gv = gv_all * g if ctx.needs_input_grad[1] else None
+        gx = (gx_all * g).sum(dim=1) if ctx.needs_input_grad[0] else None
         return gx, gv, None
 
 
