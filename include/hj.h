@@ -268,6 +268,23 @@ int32_t hj_eval(int32_t H_kind, const hj_h_params *H, int32_t J_kind, const hj_j
                 double *out_phi, void *out_yN, double *out_rho,
                 void *out_grad_v, void *out_grad_x);
 
+/* hj_lax_friedrichs -- the independent grid check of section 5: the
+ * first-order Lax-Friedrichs scheme for phi_t + H(x, grad phi) = 0,
+ * phi(x, 0) = g(x), in two space dimensions, on the grid x_i = x0 + i dx
+ * (i < nx), y_j = y0 + j dy (j < ny), nt forward-Euler steps of dt with the
+ * numerical Hamiltonian H(x, (D+x + D-x)/2, (D+y + D-y)/2) - ax (D+x -
+ * D-x)/2 - ay (D+y - D-y)/2 (one-sided differences, linear extrapolation
+ * across the boundary).  ax, ay bound |dH/dp_1|, |dH/dp_2| (stability:
+ * dt (ax/dx + ay/dy) <= 1).  H: HJ_H_QUADRATIC without drift, n = 2; g:
+ * either J kind.
+ *   phi   device double [ny, nx]: the solution at t = nt dt (row j is y_j)
+ *   work  device double [ny, nx] scratch, or NULL (the library's scratch)
+ * Enqueued on `stream`; errors as in hj_solve. */
+int32_t hj_lax_friedrichs(int32_t H_kind, const hj_h_params *H, int32_t J_kind,
+                          const hj_j_params *J, double x0, double y0, double dx, double dy,
+                          int32_t nx, int32_t ny, double dt, int32_t nt, double ax, double ay,
+                          double *phi, double *work, void *stream);
+
 /* One problem instance of a batched solve (all device arrays as in
  * hj_solve; H and J parameter arrays are host pointers copied at planning). */
 typedef struct {

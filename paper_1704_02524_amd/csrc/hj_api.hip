@@ -1308,6 +1308,36 @@ int32_t hj_solve_noalloc(int32_t H_kind, const hj_h_params* H, int32_t J_kind,
   return solve_t<float>(H, J, x, B, n, t, nsteps, guesses, &o, out_u, out_argopt, out_cert, diag);
 }
 
+int32_t hj_lax_friedrichs(int32_t H_kind, const hj_h_params* H, int32_t J_kind,
+                          const hj_j_params* J, double x0, double y0, double dx, double dy,
+                          int32_t nx, int32_t ny, double dt, int32_t nt, double ax, double ay,
+                          double* phi, double* work, void* stream) {
+  g_last_error.clear();
+  if (H_kind != HJ_H_QUADRATIC)
+    return fail(HJ_EUNSUPPORTED, "the Lax-Friedrichs solver takes the quadratic family");
+  int rc = check_problem(H_kind, H, J_kind, J, 2, 1.0, 1);
+  if (rc) return rc;
+  if (H->A) return fail(HJ_EUNSUPPORTED, "the Lax-Friedrichs solver takes no drift matrix");
+  if (nx < 3 || ny < 3 || nt < 0 || !(dx > 0.0) || !(dy > 0.0) || !(dt > 0.0) ||
+      !(ax >= 0.0) || !(ay >= 0.0) || !std::isfinite(x0) || !std::isfinite(y0))
+    return fail(HJ_EINVAL, "need nx, ny >= 3, nt >= 0, dx, dy, dt > 0, ax, ay >= 0");
+  if ((int64_t)nx * ny > ((int64_t)1 << 31))
+    return fail(HJ_EINVAL, "the grid is limited to 2^31 cells");
+  if (!phi) return fail(HJ_EINVAL, "phi is required");
+  hj_opts o = default_opts();
+  o.stream = stream;
+  if (!work) {
+    void* ws = nullptr;
+    rc = get_workspace(&o, (size_t)nx * ny * sizeof(double), &ws);
+    if (rc) return rc;
+    work = static_cast<double*>(ws);
+  }
+  const hj::PaperProblem P = paper_problem(H_kind, H, J_kind, J, 2, 1.0, 1, &o);
+  HJ_HIP(hj::launch_lax_friedrichs(P, x0, y0, dx, dy, nx, ny, dt, nt, ax, ay, phi, work,
+                                   static_cast<hipStream_t>(stream)));
+  return HJ_OK;
+}
+
 int32_t hj_eval(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j_params* J,
                 const void* x, int64_t B, int32_t n, double t, int32_t nsteps, const void* v,
                 int32_t G, const hj_opts* opts, double* out_phi, void* out_yN, double* out_rho,

@@ -51,4 +51,26 @@ hipError_t launch_eval_paper(const PaperProblem& P, const double* x, const doubl
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_lax_friedrichs(const PaperProblem& P, double x0, double y0, double dx,
+                                 double dy, int nx, int ny, double dt, int nt, double ax,
+                                 double ay, double* phi, double* work, hipStream_t st) {
+  const int block = 256;
+  const int64_t cells = (int64_t)nx * ny;
+  const unsigned grid = (unsigned)((cells + block - 1) / block);
+  // an even number of ping-pong steps ends in the array the caller reads
+  double* a = (nt % 2 == 0) ? phi : work;
+  double* b = (nt % 2 == 0) ? work : phi;
+  hipLaunchKernelGGL(k_lf_init, dim3(grid), dim3(block), 0, st, P, x0, y0, dx, dy, nx, ny, a);
+  hipError_t e = hipGetLastError();
+  for (int s = 0; s < nt && e == hipSuccess; ++s) {
+    hipLaunchKernelGGL(k_lf_step, dim3(grid), dim3(block), 0, st, P, x0, y0, dx, dy, nx, ny,
+                       dt, ax, ay, a, b);
+    e = hipGetLastError();
+    double* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  return e;
+}
+
 }  // namespace hj

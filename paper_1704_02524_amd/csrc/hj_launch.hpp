@@ -123,6 +123,12 @@ hipError_t launch_solve_paper(const PaperArgs& A, hipStream_t st);
 hipError_t launch_eval_paper(const PaperProblem& P, const double* x, const double* v, int64_t B,
                              int G, double* phi, double* rho, hipStream_t st);
 
+// Lax-Friedrichs: nt steps from phi(., 0) = g on an nx x ny grid, ping-pong
+// between phi and work; the result ends in phi.
+hipError_t launch_lax_friedrichs(const PaperProblem& P, double x0, double y0, double dx,
+                                 double dy, int nx, int ny, double dt, int nt, double ax,
+                                 double ay, double* phi, double* work, hipStream_t st);
+
 // Launch a descent kernel over A.ntask tasks.  grid_groups = 0: one task
 // group per task (no queue); otherwise a persistent launch of grid_groups
 // task groups fed by A.queue (reset by this call with a small kernel, so the

@@ -427,4 +427,56 @@ __global__ __launch_bounds__(256) void k_eval_paper(PaperProblem P, const double
   if (rho) rho[task] = r;
 }
 
+// ---------------------------------------------------------------------------
+// Lax-Friedrichs grid solver of phi_t + H(x, grad phi) = 0 in two space
+// dimensions (the independent check of section 5), H of the quadratic
+// family: phi^{k+1} = phi^k - dt [H(x, (D+x + D-x)/2, (D+y + D-y)/2)
+//   - ax (D+x - D-x)/2 - ay (D+y - D-y)/2], one-sided differences D+-,
+// linear extrapolation across the boundary.  One thread per cell, one launch
+// per time step (reads the old array, writes the new one); row j of phi is
+// y_j = y0 + j dy, column i is x_i = x0 + i dx.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lf_hamiltonian(const PaperProblem& P, double x, double y,
+                                                 double p1, double p2) {
+  const double r = x * x + y * y;
+  double c = 1.0;
+  if (P.m_kind == HJ_M_RAT)
+    c = 1.0 + P.kappa * r / (1.0 + r);
+  else if (P.m_kind == HJ_M_TANH)
+    c = 1.0 + P.kappa * dtanh(r * P.inv_s);
+  const double m = P.e == 2 ? c * c : c;
+  const double q = P.d[0] * p1 * p1 + P.d[1] * p2 * p2;
+  return 0.5 * m * q + 0.5 * P.w * r;
+}
+
+__global__ __launch_bounds__(256) void k_lf_init(PaperProblem P, double x0, double y0, double dx,
+                                                 double dy, int nx, int ny, double* phi) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= (int64_t)nx * ny) return;
+  const int i = (int)(c % nx), j = (int)(c / nx);
+  double xy[2] = {x0 + i * dx, y0 + j * dy};
+  phi[c] = paper_g<2>(P, xy);
+}
+
+__global__ __launch_bounds__(256) void k_lf_step(PaperProblem P, double x0, double y0, double dx,
+                                                 double dy, int nx, int ny, double dt,
+                                                 double ax, double ay,
+                                                 const double* __restrict__ old,
+                                                 double* __restrict__ nw) {
+  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (cell >= (int64_t)nx * ny) return;
+  const int i = (int)(cell % nx), j = (int)(cell / nx);
+  const double c = old[cell];
+  const double l = i > 0 ? old[cell - 1] : 2.0 * c - old[cell + 1];
+  const double r = i < nx - 1 ? old[cell + 1] : 2.0 * c - old[cell - 1];
+  const double d = j > 0 ? old[cell - nx] : 2.0 * c - old[cell + nx];
+  const double u = j < ny - 1 ? old[cell + nx] : 2.0 * c - old[cell - nx];
+  const double pp = (r - c) / dx, pm = (c - l) / dx;
+  const double qp = (u - c) / dy, qm = (c - d) / dy;
+  const double Hn = lf_hamiltonian(P, x0 + i * dx, y0 + j * dy, 0.5 * (pp + pm),
+                                   0.5 * (qp + qm)) -
+                    0.5 * ax * (pp - pm) - 0.5 * ay * (qp - qm);
+  nw[cell] = c - dt * Hn;
+}
+
 }  // namespace hj

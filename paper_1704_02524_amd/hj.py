@@ -95,6 +95,12 @@ def lib():
                               C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                               C.c_void_p, C.c_int32, C.POINTER(Opts), C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p]
+        L.hj_lax_friedrichs.restype = C.c_int32
+        L.hj_lax_friedrichs.argtypes = [C.c_int32, C.POINTER(HParams), C.c_int32,
+                                        C.POINTER(JParams), C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.c_int32, C.c_int32, C.c_double,
+                                        C.c_int32, C.c_double, C.c_double, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
         L.hj_workspace_size.restype = C.c_size_t
         L.hj_workspace_size.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32,
                                         C.POINTER(Opts)]
@@ -251,6 +257,20 @@ def evaluate(wl, x: torch.Tensor, v: torch.Tensor, grad: bool = False, yN: bool 
                        _ptr(out.get("grad_v")), _ptr(out.get("grad_x")))
     _check(rc)
     return out
+
+
+def lax_friedrichs(wl, x0, y0, dx, dy, nx, ny, dt, nt, ax, ay, device="cuda",
+                   stream: Optional[torch.cuda.Stream] = None):
+    """hj_lax_friedrichs: the grid solution [ny, nx] (float64, row j at y0 +
+    j dy) of the workload's H and g (n = 2) at t = nt dt."""
+    prob = Problem(wl)
+    phi = torch.empty(ny, nx, dtype=torch.float64, device=device)
+    work = torch.empty(ny, nx, dtype=torch.float64, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().hj_lax_friedrichs(prob.h_kind, C.byref(prob.H), prob.j_kind, C.byref(prob.J),
+                                   x0, y0, dx, dy, nx, ny, dt, nt, ax, ay, _ptr(phi),
+                                   _ptr(work), C.c_void_p(s.cuda_stream)))
+    return phi
 
 
 class HJFunctional(torch.autograd.Function):

@@ -280,3 +280,26 @@ def test_lax_friedrichs_converges_to_the_free_particle():
         inner = (np.abs(X) <= 1.0) & (np.abs(Y) <= 1.0)
         errs.append(np.abs(phi - exact)[inner].max())
     assert errs[1] < errs[0] and 1.6 < errs[0] / errs[1] < 2.4, errs
+
+
+def test_formula_solutions_match_the_viscosity_solution():
+    """The independent check of section 5: on the n = 2 Lax problem of the
+    benchmark (H = 1/2 c(x)^2 |p|^2, c = 1 + 0.25|x|^2/(1+|x|^2), g =
+    1/2|x|^2 - 1/2, t = 0.5), the RK4 reference's certified values at
+    scattered points and the Lax-Friedrichs grid solution differ by O(dx):
+    the difference halves with the mesh."""
+    from oracle.oracle import Oracle
+    wl = W.c0_lax_n2()
+    pts = np.array([[0.5, 0.5], [1.0, -0.5], [-1.5, 0.25], [0.0, 0.0], [1.25, 1.25]])
+    sub = wl.with_(x=pts, guesses=wl.guesses[:len(pts)])
+    ref = Oracle.from_workload(sub).solve(sub.x, sub.guesses, Oracle.opts_from_workload(sub))
+    assert (ref["cert"] == 1).all()
+    po = PaperOracle(wl.with_(mode=W.ALG1))
+    diffs = []
+    for dx in (0.04, 0.02):
+        nx = int(round(6 / dx)) + 1
+        phi = po.lax_friedrichs(-3.0, -3.0, dx, dx, nx, nx, dx / 12, int(round(6.0 / dx)),
+                                5.0, 5.0)
+        idx = np.round((pts + 3) / dx).astype(int)
+        diffs.append(np.abs(phi[idx[:, 1], idx[:, 0]] - ref["u"]).max())
+    assert diffs[0] < 0.1 and 1.7 < diffs[0] / diffs[1] < 2.4, diffs
