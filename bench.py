@@ -172,12 +172,12 @@ def run_gpu(wl, steps, warmup, label, cfg=None):
     return wall, kern_ms, host
 
 
-def run_batched(wls, steps, warmup):
+def run_batched(wls, steps, warmup, group_cfg=None):
     """Replays of one captured plan; the events bracket the whole graph on
     the stream it is launched on."""
     import torch
     from paper_1704_02524_amd import hj
-    plan = hj.BatchPlan(wls)
+    plan = hj.BatchPlan(wls, group_cfg=group_cfg)
     log(f"batched plan: {plan.info()}")
     for i in range(warmup):
         plan.run()
@@ -559,8 +559,23 @@ def main():
     if batched:
         log(f"workload {args.workload}: {len(wls)} instances, "
             f"{sum(w.B for w in wls)} points, {sum(w.B * w.G for w in wls)} tasks")
-        wall, kern, hosts, info = run_batched(wls, args.steps, args.warmup)
-        cfg = {"plan": info}
+        tuning = None
+        table = None
+        if not args.no_tune:
+            # the tuner's table against the library's default launch choices,
+            # both timed on the full plan; the faster one is measured
+            table = tune.tune_batched(wls, verbose=True)
+            ms_def = tune.time_plan(wls, None, reps=2)
+            ms_tuned = tune.time_plan(wls, table, reps=2) if table else ms_def
+            log(f"batched tuning: default {ms_def:.1f} ms, tuned {ms_tuned:.1f} ms, "
+                f"table {table}")
+            tuning = {"table": table, "default_graph_ms": ms_def, "tuned_graph_ms": ms_tuned,
+                      "gain": ms_def / ms_tuned, "used": "tuned" if ms_tuned < ms_def else
+                      "default"}
+            if ms_tuned >= ms_def:
+                table = None
+        wall, kern, hosts, info = run_batched(wls, args.steps, args.warmup, table)
+        cfg = {"plan": info, "group_cfg": table}
         n_cert = int(sum((h["cert"] == 1).sum() for h in hosts))
         k_s = float(np.mean(kern)) / 1e3
         flops = sum(algorithmic_flops(w, h["slot_fwd"], h["slot_bwd"])
@@ -588,6 +603,7 @@ def main():
                 "scope_table_count": {"flops_per_launch": flops_sv,
                                       "achieved": flops_sv / k_s / 1e12,
                                       "frac": flops_sv / k_s / 1e12 / peak}},
+            "tuning": tuning,
         }
     else:
         if args.launch is not None:
@@ -612,6 +628,8 @@ def main():
         "config": rec["config"],
         "roofline": rec["roofline"],
     }
+    if rec.get("tuning") is not None:
+        result["tuning"] = rec["tuning"]
     # the central-FD comparison: the whole n=10 workload by default; for the
     # other workloads only on request (--cd-points), since coordinate descent
     # costs 3n solves per sweep

@@ -180,7 +180,30 @@ typedef struct {
     int32_t ode;          /* HJ_RK4 or HJ_EULER                            */
     int32_t M;            /* HJ_ALG1: alpha halves every M updates (>= 1)  */
     double  momentum;     /* HJ_MOMENTUM: the heavy-ball coefficient       */
+    /* hj_batch_plan only: launch choices by dimension class (NULL: the
+     * options above for every instance); an instance takes the first entry
+     * with n <= n_max */
+    const struct hj_group_cfg_s *group_cfg;
+    int32_t n_group_cfg;
+    /* FP32 with fp64_continue: lanes per task of the FP64 continuation
+     * launch (0: those of the descent).  The shape must have the descent
+     * shape's padded dimension; the continuation runs few, long tasks, so
+     * more lanes per task shorten them.  HJ_EUNSUPPORTED if not compiled. */
+    int32_t cont_lanes_per_task;
 } hj_opts;
+
+/* Launch choices of the instances up to a dimension (an autotuner's table):
+ * lanes per task (0: the library's shape for n; with FP32 the shape also
+ * fixes one or two waves per SIMD), checkpoint interval (0: opts->ckpt_K),
+ * lane groups of the persistent launch (0: opts->max_groups), lanes per
+ * task of the FP64 continuation (0: opts->cont_lanes_per_task). */
+typedef struct hj_group_cfg_s {
+    int32_t n_max;
+    int32_t lanes_per_task;
+    int32_t ckpt_K;
+    int32_t max_groups;
+    int32_t cont_lanes_per_task;
+} hj_group_cfg;
 
 enum {
     HJ_SCHED_AUTO = 0,       /* persistent when tasks outnumber resident lanes */
@@ -306,8 +329,9 @@ typedef struct hj_batch_plan_s *hj_batch;
 
 /* hj_batch_plan -- prepare a batched solve of n_inst independent problems
  * of uneven dimension, horizon, step count and point count (the method of
- * hj_solve applied to each).  Instances are grouped by lane shape (from n)
- * and speed profile; each group runs as ONE persistent launch whose resident
+ * hj_solve applied to each).  Instances are grouped by lane shape (from n,
+ * or from the opts->group_cfg entry covering n), speed profile and launch
+ * choices; each group runs as ONE persistent launch whose resident
  * lane groups take (instance, point, guess) tasks from a queue, longest
  * instances first, and a finished group takes the next task.  The whole
  * sequence (queue resets, the descent launches, the selection) is captured

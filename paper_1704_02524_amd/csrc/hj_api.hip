@@ -176,7 +176,9 @@ struct WsLayout {
 // lanes: lanes that hold adjoint checkpoints (0: one lane group per task);
 // cont_lanes: lanes of the FP64 continuation launch (0: none)
 WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
-                bool grad, bool solve, size_t lanes = 0, size_t cont_lanes = 0) {
+                bool grad, bool solve, size_t lanes = 0, size_t cont_lanes = 0,
+                int cont_npl = 0) {
+  if (cont_npl == 0) cont_npl = s.npl;
   WsLayout L;
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
   const size_t BG = (size_t)B * (size_t)G;
@@ -208,9 +210,9 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
     off += 256;
     L.stride64 = cont_lanes;
     L.ck64 = off;
-    off += align_up(nck * 2 * s.npl * cont_lanes * 8, 256);
+    off += align_up(nck * 2 * cont_npl * cont_lanes * 8, 256);
     L.seg64 = off;
-    off += align_up((size_t)Kc * 2 * s.npl * cont_lanes * 8, 256);
+    off += align_up((size_t)Kc * 2 * cont_npl * cont_lanes * 8, 256);
   }
   L.total = off;
   return L;
@@ -534,6 +536,29 @@ int64_t dispatch_resident_continue(const Shape& s, int mk) {
   return 0;
 }
 
+// The lane shape of the FP64 continuation: the descent's, or the compiled
+// shape with the requested lanes per task and the descent shape's padded
+// dimension (the parameter rows of the problem are laid out for that
+// dimension, and the slot records are indexed by component, not by lane).
+bool cont_shape_of(const Shape& s, int lpt, Shape& cs) {
+  cs = s;
+  if (lpt == 0 || lpt == s.lpt) return true;
+  if (s.dr) return false;
+  for (const Shape& t : hj::kShapes)
+    if (t.lpt == lpt && t.npad() == s.npad()) {
+      cs = t;
+      return true;
+    }
+  return false;
+}
+
+int cont_shape_for(const Shape& s, int lpt, Shape& cs) {
+  if (cont_shape_of(s, lpt, cs)) return HJ_OK;
+  return fail(HJ_EUNSUPPORTED, "no continuation kernel with " + std::to_string(lpt) +
+                                   " lanes per task for the " + std::to_string(s.npl) + "x" +
+                                   std::to_string(s.lpt) + " descent shape");
+}
+
 // Lane groups of the FP64 continuation launch of an FP32 GD solve over ntask
 // slots (0: no continuation).
 int64_t continue_groups(const Shape& s, int mk, const hj_opts* o, int64_t ntask) {
@@ -571,18 +596,23 @@ WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nstep
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
   const int64_t ntask = B * (int64_t)G;
   *groups = schedule_groups<T>(s, mk, o->mode, o->schedule, ntask, o->max_groups);
-  *cgroups = continue_groups(s, mk, o, ntask);
+  Shape cs{};
+  if (!cont_shape_of(s, o->cont_lanes_per_task, cs)) cs = s;  // rejected by the caller
+  *cgroups = continue_groups(cs, mk, o, ntask);
   const size_t ck_lanes = *groups > 0 ? align_up((size_t)*groups * s.lpt, 256) : 0;
-  const size_t cont_lanes = *cgroups > 0 ? align_up((size_t)*cgroups * s.lpt, 256) : 0;
-  return layout(s, n, B, G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes, cont_lanes);
+  const size_t cont_lanes = *cgroups > 0 ? align_up((size_t)*cgroups * cs.lpt, 256) : 0;
+  return layout(s, n, B, G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes, cont_lanes,
+                cs.npl);
 }
 
 template <typename T>
 int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B, int n,
             double t, int nsteps, const hj_guesses* gs, const hj_opts* o, double* out_u,
             void* out_argopt, int32_t* out_cert, const hj_slot_diag* diag) {
-  Shape s{};
+  Shape s{}, cs{};
   int rc = shape_for(H, n, o->lanes_per_task, sizeof(T) == 4, s);
+  if (rc) return rc;
+  rc = cont_shape_for(s, o->cont_lanes_per_task, cs);
   if (rc) return rc;
   const int npad = s.npad();
   const int K = std::max(1, std::min(o->ckpt_K, nsteps));
@@ -677,7 +707,7 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
       CA.seg = reinterpret_cast<double*>(base + WL.seg64);
       CA.stride = WL.stride64;
       CA.queue = ctr + 8;
-      HJ_HIP(dispatch_continue(s, kernel_mk(H), CA, false, cgroups, st));
+      HJ_HIP(dispatch_continue(cs, kernel_mk(H), CA, false, cgroups, st));
     }
   }
   if (o->ev_end) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_end), st));
@@ -773,6 +803,14 @@ int check_opts(const hj_opts* o) {
   if (o->schedule < HJ_SCHED_AUTO || o->schedule > HJ_SCHED_PERSISTENT)
     return fail(HJ_EINVAL, "bad schedule");
   if (o->max_groups < 0) return fail(HJ_EINVAL, "max_groups must be >= 0");
+  if (o->cont_lanes_per_task < 0) return fail(HJ_EINVAL, "cont_lanes_per_task must be >= 0");
+  if (o->n_group_cfg < 0 || (o->n_group_cfg > 0 && !o->group_cfg))
+    return fail(HJ_EINVAL, "group_cfg must hold n_group_cfg entries");
+  for (int c = 0; c < o->n_group_cfg; ++c) {
+    const hj_group_cfg& g = o->group_cfg[c];
+    if (g.lanes_per_task < 0 || g.ckpt_K < 0 || g.max_groups < 0 || g.cont_lanes_per_task < 0)
+      return fail(HJ_EINVAL, "group_cfg entries must be >= 0");
+  }
   return HJ_OK;
 }
 
@@ -946,10 +984,14 @@ struct hj_batch_plan_s {
 
 namespace {
 
-// One launch of a plan: the instances that share a lane shape and profile.
+// One launch of a plan: the instances that share a lane shape, profile and
+// launch choices.
 struct LaunchGroup {
   Shape s;
   int mk;
+  int K = 0, maxg = 0;  // checkpoint interval, lane-group cap (0: the defaults)
+  Shape cs{};           // lane shape of the FP64 continuation
+  double work = 0.0;    // sum over tasks of n x steps (launch order)
   std::vector<int> inst;  // indices into the caller's array, longest first
   int64_t tasks = 0, points = 0, groups = 0;
   int max_steps = 0;
@@ -966,15 +1008,36 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
   // group by (shape, speed profile); within a group, longest instances first
   std::vector<LaunchGroup> lg;
   for (int i = 0; i < n_inst; ++i) {
-    Shape s{};
-    if (!pick_shape(inst[i].n, o->lanes_per_task, false, sizeof(T) == 4, s))
-      return fail(HJ_EUNSUPPORTED, "no kernel shape for instance " + std::to_string(i));
+    // the instance's launch choices: the first table entry covering its n
+    int lpt = o->lanes_per_task, K = std::max(1, o->ckpt_K), maxg = o->max_groups;
+    int clpt = o->cont_lanes_per_task;
+    for (int c = 0; c < o->n_group_cfg; ++c) {
+      const hj_group_cfg& gc = o->group_cfg[c];
+      if (inst[i].n <= gc.n_max) {
+        if (gc.lanes_per_task > 0) lpt = gc.lanes_per_task;
+        if (gc.ckpt_K > 0) K = gc.ckpt_K;
+        if (gc.max_groups > 0) maxg = gc.max_groups;
+        if (gc.cont_lanes_per_task > 0) clpt = gc.cont_lanes_per_task;
+        break;
+      }
+    }
+    Shape s{}, cs{};
+    if (!pick_shape(inst[i].n, lpt, false, sizeof(T) == 4, s))
+      return fail(HJ_EUNSUPPORTED, "no kernel shape for instance " + std::to_string(i) +
+                                       " with " + std::to_string(lpt) + " lanes per task");
+    int rc2 = cont_shape_for(s, clpt, cs);
+    if (rc2) return rc2;
     const int mk = kernel_mk(&inst[i].H);
     auto it = std::find_if(lg.begin(), lg.end(), [&](const LaunchGroup& g) {
-      return g.s.npl == s.npl && g.s.lpt == s.lpt && g.mk == mk;
+      return g.s.npl == s.npl && g.s.lpt == s.lpt && g.mk == mk && g.K == K &&
+             g.maxg == maxg && g.cs.lpt == cs.lpt;
     });
     if (it == lg.end()) {
-      lg.push_back(LaunchGroup{s, mk, {}});
+      LaunchGroup g{s, mk};
+      g.K = K;
+      g.maxg = maxg;
+      g.cs = cs;
+      lg.push_back(g);
       it = lg.end() - 1;
     }
     it->inst.push_back(i);
@@ -987,14 +1050,22 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
       g.tasks += inst[i].B * (int64_t)inst[i].guesses.G;
       g.points += inst[i].B;
       g.max_steps = std::max(g.max_steps, inst[i].nsteps);
+      g.work += (double)inst[i].B * inst[i].guesses.G * inst[i].nsteps * inst[i].n;
     }
     int64_t res = dispatch_resident<T>(g.s, g.mk, HJ_GD_ADJ);
-    if (o->max_groups > 0) res = std::min<int64_t>(res > 0 ? res : g.tasks, o->max_groups);
+    if (g.maxg > 0) res = std::min<int64_t>(res > 0 ? res : g.tasks, g.maxg);
     g.groups = std::max<int64_t>(1, std::min(res > 0 ? res : g.tasks, g.tasks));
-    g.cgroups = continue_groups(g.s, g.mk, o, g.tasks);
+    hj_opts og = *o;
+    og.max_groups = g.maxg;
+    g.cgroups = continue_groups(g.cs, g.mk, &og, g.tasks);
   }
+  // heaviest group first: the persistent launches take the chip in launch
+  // order, and the heaviest group's tail (its longest tasks, then its FP64
+  // continuation) then overlaps the lighter groups' work instead of
+  // following it
+  std::stable_sort(lg.begin(), lg.end(),
+                   [](const LaunchGroup& a, const LaunchGroup& b) { return a.work > b.work; });
   // memory layout
-  const int Kmax = std::max(1, o->ckpt_K);
   size_t off = 0;
   for (LaunchGroup& g : lg) {
     const int npad = g.s.npad();
@@ -1010,7 +1081,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
            align_up((size_t)g.tasks * nmax * tsz, 256);
     g.queue = off;
     off += 256;
-    const int K = std::max(1, std::min(Kmax, g.max_steps));
+    const int K = std::max(1, std::min(g.K, g.max_steps));
     g.stride = align_up((size_t)g.groups * g.s.lpt, 256);
     const size_t nck = (size_t)((g.max_steps + K - 1) / K) + 1;
     g.ck = off;
@@ -1022,11 +1093,11 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
       off += align_up((size_t)g.tasks * 8, 256);
       g.cont_ctr = off;
       off += 256;
-      g.stride64 = align_up((size_t)g.cgroups * g.s.lpt, 256);
+      g.stride64 = align_up((size_t)g.cgroups * g.cs.lpt, 256);
       g.ck64 = off;
-      off += align_up(nck * 2 * g.s.npl * g.stride64 * 8, 256);
+      off += align_up(nck * 2 * g.cs.npl * g.stride64 * 8, 256);
       g.seg64 = off;
-      off += align_up((size_t)K * 2 * g.s.npl * g.stride64 * 8, 256);
+      off += align_up((size_t)K * 2 * g.cs.npl * g.stride64 * 8, 256);
     }
     (void)n;
   }
@@ -1091,7 +1162,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     A.P = table[0].P;  // unused by the batched kernel except for n
     A.P.n = nmax;
     A.max_iter = o->max_iter;
-    A.K = std::max(1, std::min(Kmax, g.max_steps));
+    A.K = std::max(1, std::min(g.K, g.max_steps));
     A.cert_fp64 = o->cert_fp64;
     A.alpha0 = (T)o->alpha0;
     A.sigma = (T)o->fd_sigma;
@@ -1167,7 +1238,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
         CA.seg = reinterpret_cast<double*>(base + g.seg64);
         CA.stride = g.stride64;
         CA.queue = A.handoff_n + 8;
-        err = dispatch_continue(g.s, g.mk, CA, true, g.cgroups, st);
+        err = dispatch_continue(g.cs, g.mk, CA, true, g.cgroups, st);
       }
     }
     if (err == hipSuccess)

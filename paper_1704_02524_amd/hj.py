@@ -50,7 +50,14 @@ class Opts(C.Structure):
                 ("stream", C.c_void_p), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
                 ("ev_begin", C.c_void_p), ("ev_end", C.c_void_p), ("schedule", C.c_int32),
                 ("max_groups", C.c_int32), ("fp64_continue", C.c_int32),
-                ("ode", C.c_int32), ("M", C.c_int32), ("momentum", C.c_double)]
+                ("ode", C.c_int32), ("M", C.c_int32), ("momentum", C.c_double),
+                ("group_cfg", C.c_void_p), ("n_group_cfg", C.c_int32),
+                ("cont_lanes_per_task", C.c_int32)]
+
+
+class GroupCfg(C.Structure):
+    _fields_ = [("n_max", C.c_int32), ("lanes_per_task", C.c_int32), ("ckpt_K", C.c_int32),
+                ("max_groups", C.c_int32), ("cont_lanes_per_task", C.c_int32)]
 
 SCHED_AUTO, SCHED_STATIC, SCHED_PERSISTENT = 0, 1, 2
 
@@ -308,7 +315,11 @@ class BatchPlan:
     dtype and solve options; any n, t, N, B).  Owns the device inputs and
     outputs of every instance; run() replays the captured graph."""
 
-    def __init__(self, wls, device="cuda", diag=True, **opt_over):
+    def __init__(self, wls, device="cuda", diag=True, group_cfg=None, **opt_over):
+        """group_cfg: launch choices by dimension class, a list of dicts with
+        n_max and any of lanes_per_task, ckpt_K, max_groups,
+        cont_lanes_per_task (0 or absent: the library's choice); an instance
+        takes the first entry with n <= n_max."""
         assert len(wls) > 0
         self.wls = wls
         self.inputs, self.outputs, self._probs = [], [], []
@@ -350,6 +361,14 @@ class BatchPlan:
                                   _ptr(out["slot_v"]))
         self._arr = arr
         o = make_opts(wls[0], **opt_over)
+        if group_cfg:
+            cfgs = sorted(group_cfg, key=lambda c: c["n_max"])
+            self._gcfg = (GroupCfg * len(cfgs))(*[
+                GroupCfg(int(c["n_max"]), int(c.get("lanes_per_task", 0)),
+                         int(c.get("ckpt_K", 0)), int(c.get("max_groups", 0)),
+                         int(c.get("cont_lanes_per_task", 0))) for c in cfgs])
+            o.group_cfg = C.cast(self._gcfg, C.c_void_p)
+            o.n_group_cfg = len(cfgs)
         h = C.c_void_p()
         _check(lib().hj_batch_plan(HJ_H_QUADRATIC, HJ_J_ELLIPSOID, arr, len(wls), C.byref(o),
                                    C.byref(h)))

@@ -14,7 +14,7 @@ from __future__ import annotations
 import json
 import sys
 import os
-from typing import Dict, Optional
+from typing import Dict, List, Optional
 
 import torch
 
@@ -27,6 +27,27 @@ CACHE = os.path.join(HERE, "tuning.json")
 # lanes-per-task values compiled for each dimension bound (mirrors the shape
 # table of the library: a request the library cannot serve raises)
 LPT_CHOICES = (1, 2, 4, 8, 16)
+# the library's (components per lane, lanes per task) shapes without a drift
+# matrix; an explicit lanes-per-task request takes the one with the fewest
+# components per lane that covers n
+SHAPES = ((2, 1), (4, 1), (4, 2), (5, 2), (3, 4), (4, 4), (8, 4), (8, 8), (13, 8), (16, 8),
+          (2, 2), (8, 1), (2, 4), (10, 1), (8, 2), (4, 8), (7, 16))
+
+
+def shape_for(n: int, lpt: int):
+    fit = [s for s in SHAPES if s[1] == lpt and n <= s[0] * s[1]]
+    return min(fit) if fit else None
+
+
+def dense_lpts(n: int):
+    """Lanes-per-task values whose shape leaves no lane of a task without a
+    component."""
+    out = []
+    for lpt in LPT_CHOICES:
+        s = shape_for(n, lpt)
+        if s is not None and -(-n // s[0]) == lpt:
+            out.append(lpt)
+    return out
 
 
 def _key(wl) -> str:
@@ -121,3 +142,138 @@ def tune(wl, tune_iters: int = 20, use_cache: bool = True, verbose: bool = False
     except OSError:
         pass
     return dict(best)
+
+
+# ---------------------------------------------------------------------------
+# batched plans
+# ---------------------------------------------------------------------------
+BATCH_K = (8, 32)
+
+
+def _batch_key(wls) -> str:
+    n_cls = sorted({w.n for w in wls})
+    w = wls[0]
+    return (f"batch{len(wls)}_n{'-'.join(map(str, n_cls))}_pts{sum(x.B for x in wls)}"
+            f"_G{w.G}_dt{w.dtype}_m{w.m_kind}_q{w.quad}_f{w.formula}_it{w.max_iter}")
+
+
+def time_plan(wls, group_cfg, reps: int = 1, warm: bool = False) -> Optional[float]:
+    """Graph time (ms, best of reps) of a plan over wls."""
+    plan = None
+    try:
+        plan = hj.BatchPlan(wls, diag=False, group_cfg=group_cfg)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        if warm:
+            plan.run()
+            torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            ev[0].record()
+            plan.run()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1])
+            best = ms if best is None else min(best, ms)
+        return best
+    except hj.HJError:
+        return None
+    finally:
+        if plan is not None:
+            plan.free()
+
+
+def _default_lpt(n: int, f32: bool) -> int:
+    if f32 and 64 < n <= 112:
+        return 16
+    for npl, lpt in SHAPES[:10]:
+        if n <= npl * lpt:
+            return lpt
+    return 0
+
+
+def cont_lpts(n: int, lpt: int):
+    """Lanes-per-task values of the FP64 continuation for the descent shape
+    of (n, lpt): the compiled shapes with its padded dimension, other lane
+    counts, no lane without a component."""
+    s = shape_for(n, lpt)
+    if s is None:
+        return []
+    return sorted({t[1] for t in SHAPES if t[0] * t[1] == s[0] * s[1] and t[1] != lpt
+                   and -(-n // t[0]) == t[1]})
+
+
+def tune_batched(wls, use_cache: bool = True, verbose: bool = False,
+                 min_gain: float = 1.02) -> List[dict]:
+    """A launch table for hj_batch_plan: per dimension class, the lanes per
+    task (with FP32 this also picks the one- or two-wave build of the
+    kernel), the lanes per task of the FP64 continuation (FP32) and the
+    checkpoint interval.
+
+    The probe is the whole plan at full work.  The shape groups run as
+    concurrent graph branches whose persistent launches fill the chip in
+    turn, and a group's time is set by its longest tasks (restarts, FP64
+    continuation) as much as by its per-iteration rate, so neither a class
+    timed alone nor a shortened run predicts the plan's time.  Greedy
+    coordinate search, largest class (by work) first: lanes per task, the
+    continuation's lanes, then the interval; a change is kept when the plan
+    gets faster by min_gain."""
+    key = _batch_key(wls)
+    table = _load()
+    if use_cache and key in table:
+        return [dict(c) for c in table[key]["config"]]
+    f32 = wls[0].dtype == W.F32
+    work = {}
+    for w in wls:
+        work[w.n] = work.get(w.n, 0.0) + float(w.n) * w.nsteps * w.B * w.G
+    classes = sorted(work, key=lambda n: -work[n])
+    cur = {n: {} for n in classes}
+    log = []
+
+    def as_list(t):
+        # every class gets its entry, an empty one meaning the library's
+        # choices: an instance takes the first entry with n <= n_max, so a
+        # missing class would fall into the next larger class's entry
+        return [dict(n_max=n, **t[n]) for n in sorted(t)]
+
+    def run(t):
+        ms = time_plan(wls, as_list(t))
+        if verbose:
+            print(f"[tune] batch {as_list(t)}: {ms} ms", file=sys.stderr, flush=True)
+        log.append({"table": as_list(t), "ms": ms})
+        return ms
+
+    best = run(cur)
+    if best is None:
+        return []
+    for n in classes:
+        for lpt in dense_lpts(n):
+            if lpt == _default_lpt(n, f32):
+                continue
+            cand = {k: dict(v) for k, v in cur.items()}
+            cand[n] = {"lanes_per_task": lpt}
+            ms = run(cand)
+            if ms is not None and ms * min_gain < best:
+                cur, best = cand, ms
+    if f32 and wls[0].fp64_continue:
+        for n in classes:
+            lpt = cur[n].get("lanes_per_task", _default_lpt(n, f32))
+            for c in cont_lpts(n, lpt):
+                cand = {k: dict(v) for k, v in cur.items()}
+                cand[n] = dict(cand[n], cont_lanes_per_task=c)
+                ms = run(cand)
+                if ms is not None and ms * min_gain < best:
+                    cur, best = cand, ms
+    for n in classes:
+        for K in BATCH_K:
+            cand = {k: dict(v) for k, v in cur.items()}
+            cand[n] = dict(cand[n], ckpt_K=K)
+            ms = run(cand)
+            if ms is not None and ms * min_gain < best:
+                cur, best = cand, ms
+    out = as_list(cur)
+    table[key] = {"config": out, "ms": best, "all": log}
+    try:
+        _save(table)
+    except OSError:
+        pass
+    return out

@@ -76,6 +76,68 @@ def test_batched_equals_single_solves_and_graph_replays(hj, dtype):
     plan.free()
 
 
+# launch choices by dimension class, none of them the library's default
+_TABLE = [dict(n_max=4, lanes_per_task=2, ckpt_K=8, cont_lanes_per_task=1),
+          dict(n_max=8, lanes_per_task=1, ckpt_K=32, cont_lanes_per_task=4),
+          dict(n_max=16, lanes_per_task=2, cont_lanes_per_task=4),
+          dict(n_max=32, lanes_per_task=8, ckpt_K=4, cont_lanes_per_task=4)]
+
+
+@pytest.mark.parametrize("dtype", [W.F64, W.F32])
+def test_group_cfg_plan_equals_single_solves_with_that_launch(hj, dtype):
+    """A plan with a per-class launch table gives every instance what a
+    single solve with that class's lanes per task and checkpoint interval
+    gives it, on every replay."""
+    wls = _batch(dtype=dtype)
+    plan = hj.BatchPlan(wls, group_cfg=_TABLE)
+    assert plan.info()["launches"] == len({w.n for w in wls})
+    singles = []
+    for w in wls:
+        c = next(c for c in _TABLE if w.n <= c["n_max"])
+        over = {k: v for k, v in c.items() if k != "n_max"}
+        singles.append(_host(hj.solve(w, *hj.device_inputs(w), **over)))
+    for rep in range(2):
+        outs = plan.run()
+        torch.cuda.synchronize()
+        for w, out, ref in zip(wls, outs, singles):
+            got = _host(out)
+            np.testing.assert_array_equal(got["cert"], ref["cert"], err_msg=w.name)
+            np.testing.assert_allclose(got["u"], ref["u"], rtol=1e-13, atol=1e-13)
+            np.testing.assert_array_equal(got["slot_fwd"], ref["slot_fwd"])
+        for out in outs:
+            for v in out.values():
+                v.zero_()
+        torch.cuda.synchronize()
+    plan.free()
+
+
+def test_group_cfg_checkpoint_interval_changes_nothing(hj):
+    """The checkpoint interval only trades memory for recomputation: the
+    recomputed segments are those of the forward solve, bit for bit."""
+    wls = _batch(n_inst=6, max_points=12)
+    a = hj.BatchPlan(wls)
+    b = hj.BatchPlan(wls, group_cfg=[dict(n_max=64, ckpt_K=3)])
+    ra = [_host(o) for o in a.run()]
+    torch.cuda.synchronize()
+    rb = [_host(o) for o in b.run()]
+    torch.cuda.synchronize()
+    for x, y in zip(ra, rb):
+        for k in x:
+            np.testing.assert_array_equal(np.nan_to_num(x[k]), np.nan_to_num(y[k]), err_msg=k)
+    a.free()
+    b.free()
+
+
+def test_group_cfg_errors(hj):
+    wls = _batch(n_inst=3, max_points=4)
+    with pytest.raises(hj.HJError, match=">= 0"):
+        hj.BatchPlan(wls, group_cfg=[dict(n_max=64, ckpt_K=-1)])
+    with pytest.raises(hj.HJError, match="lanes per task"):
+        hj.BatchPlan(wls, group_cfg=[dict(n_max=64, lanes_per_task=3)])
+    with pytest.raises(hj.HJError, match="continuation"):
+        hj.BatchPlan(wls, group_cfg=[dict(n_max=64, cont_lanes_per_task=16)])
+
+
 def test_batched_matches_reference(hj):
     wls = _batch(n_inst=6, max_points=6)
     plan = hj.BatchPlan(wls)
@@ -185,3 +247,30 @@ def test_fp64_continuation_certifies_what_the_reference_certifies(hj):
         fin = ref["cert"] >= 0
         err = np.abs(got["u"][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
         assert err.max(initial=0.0) <= 1e-4, (wl.name, err)
+
+
+def test_fp64_continuation_on_a_wider_lane_shape(hj):
+    """The continuation launch on a shape with more lanes per task than the
+    descent's (the same padded dimension): the same certificates as the
+    FP64 reference, and persistent == static bit for bit on that shape."""
+    from paper_1704_02524_amd import tune
+    wls = W.c2_batched(dtype=W.F32)
+    for i, npts in ((60, 32), (7, 32), (33, 12)):
+        wl = wls[i].subset(0, npts)
+        lpt = tune._default_lpt(wl.n, True)
+        wider = [c for c in tune.cont_lpts(wl.n, lpt) if c > lpt]
+        if not wider:
+            continue
+        cl = wider[-1]
+        x, g = hj.device_inputs(wl)
+        got = _host(hj.solve(wl, x, g, cont_lanes_per_task=cl, schedule=hj.SCHED_STATIC))
+        per = _host(hj.solve(wl, x, g, cont_lanes_per_task=cl, schedule=hj.SCHED_PERSISTENT,
+                             max_groups=16))
+        for k in got:
+            np.testing.assert_array_equal(np.nan_to_num(got[k]), np.nan_to_num(per[k]),
+                                          err_msg=k)
+        ref = Oracle.from_workload(wl).solve(wl.x, wl.guesses, Oracle.opts_from_workload(wl))
+        np.testing.assert_array_equal(got["cert"], ref["cert"], err_msg=wl.name)
+        fin = ref["cert"] >= 0
+        err = np.abs(got["u"][fin] - ref["u"][fin]) / np.maximum(1, np.abs(ref["u"][fin]))
+        assert err.max(initial=0.0) <= 1e-4, (wl.name, cl, err)
