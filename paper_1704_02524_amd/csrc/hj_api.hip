@@ -177,7 +177,7 @@ struct WsLayout {
 // cont_lanes: lanes of the FP64 continuation launch (0: none)
 WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
                 bool grad, bool solve, size_t lanes = 0, size_t cont_lanes = 0,
-                int cont_npl = 0) {
+                int cont_npl = 0, int cont_K = 0) {
   if (cont_npl == 0) cont_npl = s.npl;
   WsLayout L;
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
@@ -204,15 +204,17 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
     off += align_up((size_t)Kc * 2 * s.npl * lanes * tsz, 256);
   }
   if (solve && cont_lanes > 0) {
+    const int K64 = cont_K > 0 ? std::max(1, std::min(cont_K, nsteps)) : Kc;
+    const size_t nck64 = (size_t)((nsteps + K64 - 1) / K64) + 1;
     L.handoff = off;
     off += align_up(BG * 8, 256);
     L.cont_ctr = off;
     off += 256;
     L.stride64 = cont_lanes;
     L.ck64 = off;
-    off += align_up(nck * 2 * cont_npl * cont_lanes * 8, 256);
+    off += align_up(nck64 * 2 * cont_npl * cont_lanes * 8, 256);
     L.seg64 = off;
-    off += align_up((size_t)Kc * 2 * cont_npl * cont_lanes * 8, 256);
+    off += align_up((size_t)K64 * 2 * cont_npl * cont_lanes * 8, 256);
   }
   L.total = off;
   return L;
@@ -586,6 +588,17 @@ int shape_for(const hj_h_params* H, int n, int lpt, bool f32, Shape& s) {
                                    " lanes per task for n = " + std::to_string(n));
 }
 
+// The checkpoint interval a kernel of shape s runs with: the requested one,
+// at most the step count, and for the kernels that keep the recomputed
+// segment in LDS at most their capacity plus one (the interval trades memory
+// for recomputation; results do not depend on it).
+int eff_K(int K, const Shape& s, bool f64, int nsteps) {
+  int k = std::max(1, std::min(K, nsteps));
+  const int cap = hj::seg_lds_states(s.npl, f64 ? 8 : 4, s.dr);
+  if (cap > 0) k = std::min(k, cap + 1);
+  return k;
+}
+
 // Scratch layout of hj_solve with the schedule it will use: the lane groups
 // of a persistent descent launch (0: one per task) and of the FP64
 // continuation (0: none).  A persistent launch holds checkpoints for its
@@ -593,7 +606,7 @@ int shape_for(const hj_h_params* H, int n, int lpt, bool f32, Shape& s) {
 template <typename T>
 WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nsteps,
                       const hj_opts* o, int64_t* groups, int64_t* cgroups) {
-  const int K = std::max(1, std::min(o->ckpt_K, nsteps));
+  const int K = eff_K(o->ckpt_K, s, sizeof(T) == 8, nsteps);
   const int64_t ntask = B * (int64_t)G;
   *groups = schedule_groups<T>(s, mk, o->mode, o->schedule, ntask, o->max_groups);
   Shape cs{};
@@ -602,7 +615,7 @@ WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nstep
   const size_t ck_lanes = *groups > 0 ? align_up((size_t)*groups * s.lpt, 256) : 0;
   const size_t cont_lanes = *cgroups > 0 ? align_up((size_t)*cgroups * cs.lpt, 256) : 0;
   return layout(s, n, B, G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes, cont_lanes,
-                cs.npl);
+                cs.npl, eff_K(K, cs, true, nsteps));
 }
 
 template <typename T>
@@ -615,7 +628,7 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   rc = cont_shape_for(s, o->cont_lanes_per_task, cs);
   if (rc) return rc;
   const int npad = s.npad();
-  const int K = std::max(1, std::min(o->ckpt_K, nsteps));
+  const int K = eff_K(o->ckpt_K, s, sizeof(T) == 8, nsteps);
   const int64_t ntask = B * (int64_t)gs->G;
   int64_t groups = 0, cgroups = 0;
   WsLayout WL = solve_layout<T>(s, kernel_mk(H), n, B, gs->G, nsteps, o, &groups, &cgroups);
@@ -697,7 +710,7 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
       hj::ContArgs<float> CA;
       CA.S = A;
       CA.max_iter = o->max_iter;
-      CA.K = K;
+      CA.K = eff_K(K, cs, true, nsteps);
       CA.alpha0 = o->alpha0;
       CA.eps_step = o->eps_step;
       CA.acc_rel = o->acc_rel;
@@ -724,7 +737,7 @@ int eval_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B,
   int rc = shape_for(H, n, o->lanes_per_task, sizeof(T) == 4, s);
   if (rc) return rc;
   const int npad = s.npad();
-  const int K = std::max(1, std::min(o->ckpt_K, nsteps));
+  const int K = eff_K(o->ckpt_K, s, sizeof(T) == 8, nsteps);
   const bool grad = out_gv || out_gx;
   WsLayout WL = layout(s, n, B, G, nsteps, o->dtype, o->mode, K, grad, false);
   void* ws = nullptr;
@@ -1081,7 +1094,8 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
            align_up((size_t)g.tasks * nmax * tsz, 256);
     g.queue = off;
     off += 256;
-    const int K = std::max(1, std::min(g.K, g.max_steps));
+    const int K = eff_K(g.K, g.s, tsz == 8, g.max_steps);
+    const int K64 = eff_K(K, g.cs, true, g.max_steps);
     g.stride = align_up((size_t)g.groups * g.s.lpt, 256);
     const size_t nck = (size_t)((g.max_steps + K - 1) / K) + 1;
     g.ck = off;
@@ -1093,11 +1107,12 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
       off += align_up((size_t)g.tasks * 8, 256);
       g.cont_ctr = off;
       off += 256;
+      const size_t nck64 = (size_t)((g.max_steps + K64 - 1) / K64) + 1;
       g.stride64 = align_up((size_t)g.cgroups * g.cs.lpt, 256);
       g.ck64 = off;
-      off += align_up(nck * 2 * g.cs.npl * g.stride64 * 8, 256);
+      off += align_up(nck64 * 2 * g.cs.npl * g.stride64 * 8, 256);
       g.seg64 = off;
-      off += align_up((size_t)K * 2 * g.cs.npl * g.stride64 * 8, 256);
+      off += align_up((size_t)K64 * 2 * g.cs.npl * g.stride64 * 8, 256);
     }
     (void)n;
   }
@@ -1162,7 +1177,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     A.P = table[0].P;  // unused by the batched kernel except for n
     A.P.n = nmax;
     A.max_iter = o->max_iter;
-    A.K = std::max(1, std::min(g.K, g.max_steps));
+    A.K = eff_K(g.K, g.s, tsz == 8, g.max_steps);
     A.cert_fp64 = o->cert_fp64;
     A.alpha0 = (T)o->alpha0;
     A.sigma = (T)o->fd_sigma;
@@ -1228,7 +1243,7 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
         hj::ContArgs<float> CA;
         CA.S = A;
         CA.max_iter = o->max_iter;
-        CA.K = A.K;
+        CA.K = eff_K(A.K, g.cs, true, g.max_steps);
         CA.alpha0 = o->alpha0;
         CA.eps_step = o->eps_step;
         CA.acc_rel = o->acc_rel;
@@ -1436,7 +1451,6 @@ int32_t hj_eval(int32_t H_kind, const hj_h_params* H, int32_t J_kind, const hj_j
 size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const hj_opts* opts) {
   if (n < 1 || n > HJ_MAX_N || B < 0 || G < 1 || nsteps < 1) return 0;
   hj_opts o = opts ? *opts : default_opts();
-  const int K = std::max(1, std::min(o.ckpt_K, nsteps));
   // the largest of what hj_solve and hj_eval (with gradients) need, with or
   // without a drift matrix
   size_t need = 0;
@@ -1450,7 +1464,8 @@ size_t hj_workspace_size(int32_t n, int64_t B, int32_t G, int32_t nsteps, const 
                        : solve_layout<float>(s, mk, n, B, G, nsteps, &o, &g, &cg);
       need = std::max(need, a.total);
     }
-    WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode, K, true, false);
+    WsLayout b = layout(s, n, B, G, nsteps, o.dtype, o.mode,
+                        eff_K(o.ckpt_K, s, o.dtype == HJ_F64, nsteps), true, false);
     need = std::max(need, b.total);
   }
   return need;

@@ -203,6 +203,28 @@ template <int NPL, typename T> __device__ __forceinline__ T tree_sum(const T (&a
 
 
 // ---------------------------------------------------------------------------
+// LDS plan of the FP64 vector kernels
+// ---------------------------------------------------------------------------
+// The FP64 descent kernels without drift run one 256-lane block per CU (one
+// wave per SIMD), so a block may take the whole 160 KiB of LDS: 640 bytes a
+// lane.  They keep there what a gradient sweep does not touch (the point x,
+// the iterate v and the last gradient: 3 npl values a lane, stashed around
+// the sweep to free registers) and the states of the checkpointed
+// trajectory that the sweep recomputes (2 npl values each), which would
+// otherwise go to HBM and back once per step.  The number of segment states
+// that fit, at most 15, bounds the checkpoint interval of these kernels at
+// one more than that (n = 10 on one lane: 2 states, interval 3).  Host and
+// device both use this function.
+constexpr int kLdsBlockBytes = 160 * 1024;
+constexpr int seg_lds_states(int npl, int tsize, bool dr) {
+  return (tsize != 8 || dr)
+             ? 0
+             : ((kLdsBlockBytes - 3 * npl * 8 * 256) / (2 * npl * 8 * 256) < 15
+                    ? (kLdsBlockBytes - 3 * npl * 8 * 256) / (2 * npl * 8 * 256)
+                    : 15);
+}
+
+// ---------------------------------------------------------------------------
 // compile-time configuration of a kernel instance
 // ---------------------------------------------------------------------------
 // T: arithmetic type; NPL: components per lane; LPT: lanes per task;
@@ -245,6 +267,11 @@ struct Cfg {
   // (measured).  FP64 and wider FP32 shapes lose more to spills at two
   // waves than they gain.
   static constexpr int kWaves = (!DR && sizeof(T) == 4 && (LPT == 16 || NPL <= 5)) ? 2 : 1;
+  // segment states held in LDS (0: the segment goes to the global scratch)
+  // and the stash of x, v and the gradient around a sweep (with them)
+  static constexpr int kSegLds = seg_lds_states(NPL, (int)sizeof(T), DR);
+  static constexpr bool kStash = kSegLds > 0;
+  static_assert(kSegLds == 0 || kWaves == 1, "the LDS plan assumes one block per CU");
 };
 
 // Sum / max over the lanes of a task group.
@@ -478,8 +505,10 @@ __device__ __forceinline__ void reduce_rq(const typename C::T (&G)[NT][C::NPL],
 // folding each stage into y directly rounds four times at the scale of y,
 // which doubles the objective's rounding noise and, near an optimum, makes
 // the step test fail on noise (measured on the n=10 workload).  With drift,
-// A G and A^T P come from the matrix cores and enter the same updates
-// through one more FMA each.
+// A G and A^T P come from the matrix cores; there the stage derivative K is
+// formed explicitly (two FMAs per component) and enters the stage sum and
+// the next stage state through one FMA each, five or seven operations per
+// component and stage instead of nine.
 template <class C, int NT, bool QUAD>
 __device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const LaneParams<C>& L,
                                          typename C::T (&g)[NT][C::NPL],
@@ -517,21 +546,31 @@ __device__ __forceinline__ void rk4_step(const Problem<typename C::T>& P, const 
       const T cx = q[t] * m1[t] + P.w;
       const T ag_c = -(bw * m[t]), ap_c = bw * cx;  // stage-sum coefficients
       const T gn_c = -(cn * m[t]), pn_c = cn * cx;  // next-stage coefficients
+      if constexpr (C::DR) {
+        // with drift the stage derivative K = (-(A G + m D P), A^T P + cx G)
+        // is formed once (two FMAs) and enters the stage sum and the next
+        // stage state through one FMA each
 #pragma unroll
-      for (int k = 0; k < NPL; ++k) {
-        T ag0 = s == 0 ? T(0) : ag[t][k], ap0 = s == 0 ? T(0) : ap[t][k];
-        T gb = g[t][k], pb = p[t][k];
-        if constexpr (C::DR) {
-          ag0 = fmaT(-bw, AG[t][k], ag0);
-          ap0 = fmaT(bw, ATP[t][k], ap0);
-          gb = fmaT(-cn, AG[t][k], gb);
-          pb = fmaT(cn, ATP[t][k], pb);
+        for (int k = 0; k < NPL; ++k) {
+          const T kg = fmaT(-m[t], dp[t][k], -AG[t][k]);
+          const T kp = fmaT(cx, G[t][k], ATP[t][k]);
+          ag[t][k] = s == 0 ? kg : fmaT(bw, kg, ag[t][k]);
+          ap[t][k] = s == 0 ? kp : fmaT(bw, kp, ap[t][k]);
+          if (s < 3) {
+            G[t][k] = fmaT(cn, kg, g[t][k]);
+            Pp[t][k] = fmaT(cn, kp, p[t][k]);
+          }
         }
-        ag[t][k] = fmaT(ag_c, dp[t][k], ag0);
-        ap[t][k] = fmaT(ap_c, G[t][k], ap0);
-        if (s < 3) {
-          Pp[t][k] = fmaT(pn_c, G[t][k], pb);
-          G[t][k] = fmaT(gn_c, dp[t][k], gb);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+          const T ag0 = s == 0 ? T(0) : ag[t][k], ap0 = s == 0 ? T(0) : ap[t][k];
+          ag[t][k] = fmaT(ag_c, dp[t][k], ag0);
+          ap[t][k] = fmaT(ap_c, G[t][k], ap0);
+          if (s < 3) {
+            Pp[t][k] = fmaT(pn_c, G[t][k], p[t][k]);
+            G[t][k] = fmaT(gn_c, dp[t][k], g[t][k]);
+          }
         }
       }
     }
@@ -792,8 +831,10 @@ __device__ __forceinline__ void reverse_step_stored(const Problem<typename C::T>
       for (int k = 0; k < NPL; ++k) {
         const T gs = s ? YG[s - 1][k] : g[k];
         const T ps = s ? YP[s - 1][k] : p[k];
-        YG[s][k] = fmaT(gn_c, L.dk(k) * ps, fmaT(-cn, AG[k], g[k]));
-        YP[s][k] = fmaT(pn_c, gs, fmaT(cn, ATP[k], p[k]));
+        const T kg = fmaT(-S[s].m, L.dk(k) * ps, -AG[k]);  // as in rk4_step
+        const T kp = fmaT(cx, gs, ATP[k]);
+        YG[s][k] = fmaT(cn, kg, g[k]);
+        YP[s][k] = fmaT(cn, kp, p[k]);
       }
     } else {
 #pragma unroll
@@ -985,6 +1026,14 @@ __device__ __forceinline__ void backward(const Problem<typename C::T>& P, const 
   constexpr int NPL = C::NPL;
   const bool aug = (P.quad == HJ_RK4AUG);
   const int nseg = (P.N + K - 1) / K;
+  // the recomputed states y_{k0+1} .. y_{k1-1} of a segment: in LDS
+  // (C::kSegLds states; the host keeps K <= C::kSegLds + 1) or in the
+  // global scratch, in the same blocked layout
+  constexpr int SL = C::kSegLds;
+  __shared__ T s_seg[SL > 0 ? SL * 2 * NPL * 256 : 1];
+  T* const segp = SL > 0 ? s_seg : seg;
+  const size_t sstride = SL > 0 ? 256 : stride;
+  const size_t slane = SL > 0 ? (size_t)threadIdx.x : lane;
   T lg[NPL], lp[NPL], g[NPL], p[NPL];
   load_state<T, NPL>(ck, stride, lane, nseg, g, p);  // y_N
 #pragma unroll
@@ -997,21 +1046,13 @@ __device__ __forceinline__ void backward(const Problem<typename C::T>& P, const 
       lp[k] = L.a2(k) * p[k];
     }
   }
-  // (ng, np_): the next state the sweep needs, loaded one step ahead so
-  // that the memory latency overlaps the arithmetic of the current step
-  T ng[NPL], np_[NPL];
-  load_state<T, NPL>(ck, stride, lane, nseg - 1, ng, np_);
   if (!aug) add_node_grad<C>(P, L, g, p, T(0.5) * P.h, lg, lp);
   for (int c = nseg - 1; c >= 0; --c) {
     const int k0 = c * K;
     const int k1 = (k0 + K < P.N) ? k0 + K : P.N;
     // recompute y_{k0+1} .. y_{k1-1} from checkpoint c with the forward's
     // own step function
-#pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      g[k] = ng[k];
-      p[k] = np_[k];
-    }
+    load_state<T, NPL>(ck, stride, lane, c, g, p);
     for (int j = k0 + 1; j < k1; ++j) {
       T gg[1][NPL], pp[1][NPL], dummy[1] = {T(0)};
 #pragma unroll
@@ -1025,26 +1066,18 @@ __device__ __forceinline__ void backward(const Problem<typename C::T>& P, const 
         g[k] = gg[0][k];
         p[k] = pp[0][k];
       }
-      store_state<T, NPL>(seg, stride, lane, j - k0, g, p);
+      store_state<T, NPL>(segp, sstride, slane, j - k0 - 1, g, p);
     }
-    // reverse sweep over the segment, starting from y_{k1-1} (in registers)
-#pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      ng[k] = g[k];
-      np_[k] = p[k];
-    }
+    // reverse sweep over the segment, from y_{k1-1} (in registers); each
+    // earlier state is loaded where its step needs it (no state is carried
+    // ahead: the registers are worth more than the hidden latency)
     for (int j = k1 - 1; j >= k0; --j) {
-#pragma unroll
-      for (int k = 0; k < NPL; ++k) {
-        g[k] = ng[k];
-        p[k] = np_[k];
+      if (j < k1 - 1) {
+        if (j > k0)
+          load_state<T, NPL>(segp, sstride, slane, j - k0 - 1, g, p);
+        else
+          load_state<T, NPL>(ck, stride, lane, c, g, p);
       }
-      if (j - 1 > k0)
-        load_state<T, NPL>(seg, stride, lane, j - 1 - k0, ng, np_);
-      else if (j - 1 == k0)
-        load_state<T, NPL>(ck, stride, lane, c, ng, np_);
-      else if (c > 0)
-        load_state<T, NPL>(ck, stride, lane, c - 1, ng, np_);  // next segment's start
       reverse_step<C>(P, L, g, p, aug, lg, lp);
       if (!aug) add_node_grad<C>(P, L, g, p, j == 0 ? T(0.5) * P.h : P.h, lg, lp);
     }

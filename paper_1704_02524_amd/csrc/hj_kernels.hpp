@@ -101,6 +101,51 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C0::T> A) {
   }
 }
 
+// The gradient sweep of a descent iteration: gt = d(objective)/dv at v.
+// With C::kStash the point x, the iterate v and the last gradient g wait in
+// LDS while the sweep runs (the sweep reads x and v on its last line only,
+// and g not at all), which frees 3 NPL values of registers for it; every
+// lane reads back what it wrote, so no barrier is needed, and the result is
+// the same bit for bit.
+template <class C>
+__device__ __forceinline__ void grad_sweep(const Problem<typename C::T>& P,
+                                           const LaneParams<C>& L, typename C::T (&x)[C::NPL],
+                                           typename C::T (&v)[C::NPL],
+                                           typename C::T (&g)[C::NPL], const typename C::T* ck,
+                                           typename C::T* seg, size_t stride, size_t lane, int K,
+                                           typename C::T (&gt)[C::NPL]) {
+  using T = typename C::T;
+  constexpr int NPL = C::NPL;
+  T gx[NPL];
+  if constexpr (C::kStash) {
+    __shared__ T s_st[3 * NPL * 256];
+    T* const sx = s_st + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      sx[k * 256] = x[k];
+      sx[(NPL + k) * 256] = v[k];
+      sx[(2 * NPL + k) * 256] = g[k];
+    }
+    // the values now live in LDS only: the compiler may neither keep them
+    // in registers across the sweep nor skip the reloads
+    asm volatile("" ::: "memory");
+    T z[NPL];
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) z[k] = T(0);
+    backward<C>(P, L, z, z, ck, seg, stride, lane, K, gt, gx);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) {
+      x[k] = sx[k * 256];
+      v[k] = sx[(NPL + k) * 256];
+      g[k] = sx[(2 * NPL + k) * 256];
+      if (P.formula == HJ_HOPF) gt[k] -= x[k];  // as backward's last line
+    }
+  } else {
+    backward<C>(P, L, x, v, ck, seg, stride, lane, K, gt, gx);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // task context: the problem, query point and guesses of the task a lane
 // group is working on.  Single problem: the problem lives in the kernel
@@ -489,8 +534,8 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
     }
     const bool need_grad = acc && isfinite(phi);
     if (wave_if<C>(need_grad)) {
-      T gt[NPL], gx[NPL];
-      backward<C>(P, tc.L, tc.x, v, A.ck, A.seg, A.stride, lane, A.K, gt, gx);
+      T gt[NPL];
+      grad_sweep<C>(P, tc.L, tc.x, v, g, A.ck, A.seg, A.stride, lane, A.K, gt);
       if (need_grad) {
 #pragma unroll
         for (int k = 0; k < NPL; ++k) g[k] = gt[k];
@@ -679,8 +724,8 @@ __global__ __launch_bounds__(256, 1) void k_continue_gd(ContArgs<float> A) {
     }
     const bool need_grad = acc && isfinite(phi);
     if (wave_if<C>(need_grad)) {
-      double gt[NPL], gx[NPL];
-      backward<C>(P, tc.L, tc.x, v, A.ck, A.seg, A.stride, lane, A.K, gt, gx);
+      double gt[NPL];
+      grad_sweep<C>(P, tc.L, tc.x, v, g, A.ck, A.seg, A.stride, lane, A.K, gt);
       if (need_grad) {
 #pragma unroll
         for (int k = 0; k < NPL; ++k) g[k] = gt[k];

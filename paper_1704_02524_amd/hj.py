@@ -291,7 +291,9 @@ class HJFunctional(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, v, wl):
-        need = torch.is_grad_enabled() and (x.requires_grad or v.requires_grad)
+        # (autograd runs forward with gradients disabled: ask ctx which
+        # inputs will want one)
+        need = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
         out = evaluate(wl, x.detach().contiguous(), v.detach().contiguous(), grad=need)
         if need:
             ctx.save_for_backward(out["grad_x"], out["grad_v"])
