@@ -647,12 +647,13 @@ def main():
             result["cpu_baseline"] = cpu_baseline_slots(wls, args.cpu_budget)
         log(f"CPU: {result['cpu_baseline']['value']:.3f} certified solves/s")
     # the metric's second dimension: the n=32 linear-drift workload (65536
-    # points, 8 guesses, 256 steps, checkpoint interval 16 as configured) in
-    # the same run, with its own matrix-core roofline, central-FD comparison
-    # on a prefix of the points and CPU baseline
+    # points, 8 guesses, 256 steps; checkpoint interval 3, the most the FP64
+    # drift kernel's LDS segment holds) in the same run, with its own
+    # matrix-core roofline, central-FD comparison on a prefix of the points
+    # and CPU baseline
     if args.workload == "hopf_n10" and not args.no_n32:
         w32 = W.c3_drift_n32()
-        cfg32 = {"ckpt_K": 16}
+        cfg32 = {"ckpt_K": 3}
         rec32, wall32, host32 = measure_single(w32, "lax_n32_drift", 2, 1, cfg32)
         if not args.no_cd and args.n32_cd_points > 0:
             rec32.update(cd_comparison(w32, host32, wall32, args.n32_cd_points, False))

@@ -594,7 +594,7 @@ int shape_for(const hj_h_params* H, int n, int lpt, bool f32, Shape& s) {
 // for recomputation; results do not depend on it).
 int eff_K(int K, const Shape& s, bool f64, int nsteps) {
   int k = std::max(1, std::min(K, nsteps));
-  const int cap = hj::seg_lds_states(s.npl, f64 ? 8 : 4, s.dr);
+  const int cap = hj::seg_lds_states(s.npl, s.lpt, f64 ? 8 : 4, s.dr);
   if (cap > 0) k = std::min(k, cap + 1);
   return k;
 }

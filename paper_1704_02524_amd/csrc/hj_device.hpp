@@ -203,25 +203,39 @@ template <int NPL, typename T> __device__ __forceinline__ T tree_sum(const T (&a
 
 
 // ---------------------------------------------------------------------------
-// LDS plan of the FP64 vector kernels
+// LDS plan of the one-wave-per-SIMD kernels
 // ---------------------------------------------------------------------------
-// The FP64 descent kernels without drift run one 256-lane block per CU (one
-// wave per SIMD), so a block may take the whole 160 KiB of LDS: 640 bytes a
-// lane.  They keep there what a gradient sweep does not touch (the point x,
-// the iterate v and the last gradient: 3 npl values a lane, stashed around
-// the sweep to free registers) and the states of the checkpointed
-// trajectory that the sweep recomputes (2 npl values each), which would
-// otherwise go to HBM and back once per step.  The number of segment states
-// that fit, at most 15, bounds the checkpoint interval of these kernels at
-// one more than that (n = 10 on one lane: 2 states, interval 3).  Host and
-// device both use this function.
+// Waves per SIMD a descent kernel is compiled for (register budget 512 /
+// waves per lane): FP32 without drift at two where at most 5 components sit
+// on a lane or 16 lanes share a task (they fit 256 registers), one otherwise.
+constexpr int kernel_waves(int npl, int lpt, int tsize, bool dr) {
+  return (!dr && tsize == 4 && (lpt == 16 || npl <= 5)) ? 2 : 1;
+}
+// Bytes of the matrix-core operand table and weights a drift kernel stages.
+constexpr int drift_lds_bytes(int npl, int tsize, bool dr) {
+  return dr ? (2 * (npl / 4) * npl * 64 + 4 * npl) * tsize : 0;
+}
+// A one-wave kernel runs one 256-lane block per CU, so a block may take the
+// whole 160 KiB of LDS.  Beside the drift table it keeps there what a
+// gradient sweep does not touch (the point x, the iterate v and the last
+// gradient: 3 npl values a lane, stashed around the sweep to free
+// registers) and the states of the checkpointed trajectory that the sweep
+// recomputes (2 npl values each), which would otherwise go to HBM and back
+// once per step.  The number of segment states that fit, at most 15,
+// bounds the checkpoint interval of these kernels at one more than that
+// (FP64 n = 10 on one lane: 2 states, interval 3; FP64 n = 32 with drift:
+// 2 states, interval 3).  Two-wave kernels, and shapes where not even one
+// state fits beside the stash, keep both in HBM and registers.
+// Host and device both use this function.
 constexpr int kLdsBlockBytes = 160 * 1024;
-constexpr int seg_lds_states(int npl, int tsize, bool dr) {
-  return (tsize != 8 || dr)
+constexpr int seg_lds_fit(int npl, int tsize, bool dr) {
+  return (kLdsBlockBytes - drift_lds_bytes(npl, tsize, dr) - 3 * npl * tsize * 256) /
+         (2 * npl * tsize * 256);
+}
+constexpr int seg_lds_states(int npl, int lpt, int tsize, bool dr) {
+  return kernel_waves(npl, lpt, tsize, dr) != 1 || seg_lds_fit(npl, tsize, dr) < 1
              ? 0
-             : ((kLdsBlockBytes - 3 * npl * 8 * 256) / (2 * npl * 8 * 256) < 15
-                    ? (kLdsBlockBytes - 3 * npl * 8 * 256) / (2 * npl * 8 * 256)
-                    : 15);
+             : (seg_lds_fit(npl, tsize, dr) < 15 ? seg_lds_fit(npl, tsize, dr) : 15);
 }
 
 // ---------------------------------------------------------------------------
@@ -266,10 +280,10 @@ struct Cfg {
   // out of the RK4 loops; there the second wave's latency hiding pays
   // (measured).  FP64 and wider FP32 shapes lose more to spills at two
   // waves than they gain.
-  static constexpr int kWaves = (!DR && sizeof(T) == 4 && (LPT == 16 || NPL <= 5)) ? 2 : 1;
+  static constexpr int kWaves = kernel_waves(NPL, LPT, (int)sizeof(T), DR);
   // segment states held in LDS (0: the segment goes to the global scratch)
   // and the stash of x, v and the gradient around a sweep (with them)
-  static constexpr int kSegLds = seg_lds_states(NPL, (int)sizeof(T), DR);
+  static constexpr int kSegLds = seg_lds_states(NPL, LPT, (int)sizeof(T), DR);
   static constexpr bool kStash = kSegLds > 0;
   static_assert(kSegLds == 0 || kWaves == 1, "the LDS plan assumes one block per CU");
 };

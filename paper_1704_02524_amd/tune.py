@@ -70,10 +70,33 @@ def _save(table: Dict[str, dict]) -> None:
     os.replace(tmp, CACHE)
 
 
+def seg_lds_states(npl: int, lpt: int, tsize: int, dr: bool) -> int:
+    """Segment states a library kernel holds in LDS (the library's own
+    formula): 0 where the segment goes to HBM (the two-wave kernels)."""
+    if not dr and tsize == 4 and (lpt == 16 or npl <= 5):
+        return 0
+    table = (2 * (npl // 4) * npl * 64 + 4 * npl) * tsize if dr else 0
+    fit = (160 * 1024 - table - 3 * npl * tsize * 256) // (2 * npl * tsize * 256)
+    return 0 if fit < 1 else min(15, fit)
+
+
+DRIFT_NPL = (4, 8, 16)
+
+
+def effective_K(wl, lpt: int, K: int) -> int:
+    """The checkpoint interval the library runs a launch with."""
+    k = max(1, min(K, wl.nsteps))
+    tsize = 8 if wl.dtype == W.F64 else 4
+    if wl.A is not None:
+        npl = next(p for p in DRIFT_NPL if wl.n <= 4 * p)
+        cap = seg_lds_states(npl, 4, tsize, True)
+    else:
+        s = shape_for(wl.n, lpt)
+        cap = seg_lds_states(s[0], s[1], tsize, False) if s else 0
+    return min(k, cap + 1) if cap > 0 else k
+
+
 def candidates(wl):
-    ks = [None]
-    if wl.mode == W.GD_ADJ:
-        ks = sorted({1, 4, 16, min(wl.ckpt_K, wl.nsteps)})
     out = []
     # a drift matrix runs on the matrix-core layout: 4 lanes per task only
     lpts = (4,) if wl.A is not None else LPT_CHOICES
@@ -82,6 +105,11 @@ def candidates(wl):
             continue
         if wl.A is None and lpt > 1 and wl.n <= lpt:  # lanes without a component
             continue
+        ks = [None]
+        if wl.mode == W.GD_ADJ:
+            # intervals the library would run differently (it caps the
+            # interval of the kernels that recompute segments in LDS)
+            ks = sorted({effective_K(wl, lpt, k) for k in (1, 4, 16, wl.ckpt_K)})
         for K in ks:
             out.append(dict(lanes_per_task=lpt, **({} if K is None else {"ckpt_K": K})))
     return out
