@@ -452,6 +452,23 @@ def test_solve_selection_and_fallbacks():
         np.testing.assert_array_equal(res["argopt"][b], res["slot_v"][b, k])
 
 
+def test_slot_stops_at_its_first_certified_attempt():
+    """Section 5's independent trials stop once a trial is certified: a slot
+    whose first guess certifies runs one attempt, with the work of that one
+    descent only."""
+    wl = W.c1_hopf_n10(B=2)
+    wl = wl.with_(guesses=wl.guesses[:, :1])
+    O = Oracle.opts_from_workload(wl)
+    o = Oracle.from_workload(wl)
+    res = o.solve(wl.x, wl.guesses, O)
+    for b in range(2):
+        one = o.descend(wl.x[b], wl.guesses[b, 0, 0], O)
+        assert res["slot_cert"][b, 0] == 1
+        assert res["slot_attempts"][b, 0] == 1
+        assert res["slot_fwd"][b, 0] == one["n_fwd"]
+        assert res["slot_phi"][b, 0] == one["phi"]
+
+
 def test_ill_posed_hopf_instance_is_not_certified():
     """With a_1^2 < c t the Hopf objective is unbounded below in v_1; every
     run must end diverged or uncertified, never certified."""

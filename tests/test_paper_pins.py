@@ -127,6 +127,44 @@ def test_rk4_option_converges_at_fourth_order():
     assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12, errs
 
 
+@pytest.mark.parametrize("m_kind,e", [(W.M_CONST, 1), (W.M_RAT, 1), (W.M_RAT, 2),
+                                       (W.M_TANH, 1), (W.M_TANH, 2)])
+def test_quadratic_hamiltonian_derivatives(m_kind, e):
+    """H_x and H_p of the state-dependent quadratic family against central
+    differences of H itself (every speed profile, c and c^2)."""
+    rng = np.random.default_rng(5)
+    n = 3
+    wl = _wl(n=n, m_kind=m_kind, e=e, kappa=0.7, s=1.3, w=-0.4, d=np.array([-1.0, 0.5, 2.0]))
+    o = PaperOracle(wl)
+    h = 1e-6
+    for _ in range(4):
+        x, p = rng.normal(size=n), rng.normal(size=n)
+        Hx, Hp = o.grads(x, p)
+        for i in range(n):
+            ei = np.zeros(n)
+            ei[i] = h
+            fx = (o.hamiltonian(x + ei, p) - o.hamiltonian(x - ei, p)) / (2 * h)
+            fp = (o.hamiltonian(x, p + ei) - o.hamiltonian(x, p - ei)) / (2 * h)
+            assert Hx[i] == pytest.approx(fx, rel=1e-7, abs=1e-8)
+            assert Hp[i] == pytest.approx(fp, rel=1e-7, abs=1e-8)
+
+
+def test_hopf_solve_reports_minus_the_minimum():
+    """u = -min G for the Hopf functional: with an x-independent H the Euler
+    characteristics are exact straight lines, so the discrete problem has
+    the closed form of section 3.4's first example, u = 1/2 sum x_i^2 /
+    (a_i^2 + t d_i) + j0, and hjp_solve must return it with its sign."""
+    a = np.array([1.5, 2.0])
+    d = np.array([-1.0, 1.0])
+    wl = _wl(t=0.5, nsteps=9, d=d, a=a, j0=-0.3, formula=W.HOPF, alpha0=1 / 3,
+             fd_sigma=1e-8, eps_step=1e-12, cert_tol=1e-5)
+    x = np.array([[0.8, -1.1], [-0.4, 0.3]])
+    r = PaperOracle(wl).solve(x, np.zeros((2, 1, 1, 2)))
+    exact = 0.5 * (x ** 2 / (a ** 2 + 0.5 * d)).sum(axis=1) - 0.3
+    assert (r["cert"] == 1).all()
+    np.testing.assert_allclose(r["u"], exact, atol=1e-6)
+
+
 def _norm_wl(n=2, **kw):
     mu = np.zeros(n)
     mu[:2] = 1.0
@@ -262,13 +300,36 @@ def test_momentum_descent_reaches_the_closed_form():
     assert (r["n_eval"] - 1) % 3 == 0
 
 
+def test_momentum_iterates_follow_the_heavy_ball_recurrence():
+    """For the free particle the Euler objective is exactly quadratic in v,
+    F(v) = 1/2|x - t v|^2 + 1/2 t |v|^2 - 1/2 with Hessian lambda = t^2 + t,
+    so heavy-ball iterates obey v_{k+1} - v* = (1 + beta - alpha lambda)
+    (v_k - v*) - beta (v_{k-1} - v*), v* = x / (1 + t) (the forward
+    difference adds lambda sigma / 2 to every gradient component)."""
+    t, alpha, beta, sig = 0.6, 0.3, 0.5, 1e-7
+    lam = t * t + t
+    x = np.array([0.7, -1.3])
+    v0 = np.array([1.5, 1.5])
+    vs = x / (1 + t)
+    ref = [v0, v0]
+    for _ in range(3):
+        vk, vkm = ref[-1], ref[-2]
+        g = lam * (vk - vs) + 0.5 * lam * sig
+        ref.append(vk - alpha * g + beta * (vk - vkm))
+    for k in (1, 2, 3):
+        wl = _wl(t=t, nsteps=7, mode=W.MOMENTUM, alpha0=alpha, momentum=beta,
+                 acc_rel=1e-15, eps_step=1e-14, max_iter=k, fd_sigma=sig)
+        r = PaperOracle(wl).descend(x, v0)
+        np.testing.assert_allclose(r["v"], ref[k + 1], atol=1e-7)
+
+
 def test_lax_friedrichs_converges_to_the_free_particle():
     """phi_t + 1/2|grad phi|^2 = 0, phi(., 0) = 1/2|x|^2 - 1/2 has the
     solution |x|^2/(2(1+t)) - 1/2; the first-order Lax-Friedrichs scheme
     converges to it at first order in the mesh (interior points)."""
     wl = _wl()
     o = PaperOracle(wl)
-    errs = []
+    errs, edge = [], []
     for dx in (0.04, 0.02):
         nx = int(round(4.0 / dx)) + 1
         dt = dx / 5.0
@@ -278,8 +339,20 @@ def test_lax_friedrichs_converges_to_the_free_particle():
         X, Y = np.meshgrid(g1, g1, indexing="xy")
         exact = (X ** 2 + Y ** 2) / (2 * 1.5) - 0.5
         inner = (np.abs(X) <= 1.0) & (np.abs(Y) <= 1.0)
-        errs.append(np.abs(phi - exact)[inner].max())
+        err = np.abs(phi - exact)
+        errs.append(err[inner].max())
+        # the characteristics leave the square, so the boundary rule (linear
+        # extrapolation of the neighbour across the edge) keeps first order
+        # up to and on the edge
+        edge.append(np.r_[err[0], err[-1], err[:, 0], err[:, -1]].max())
+        # H and g are even in each coordinate and symmetric under x <-> y, and
+        # the stencil and the boundary rule respect that on this grid
+        scale = np.abs(phi).max()
+        np.testing.assert_allclose(phi, phi[:, ::-1], rtol=0, atol=1e-12 * scale)
+        np.testing.assert_allclose(phi, phi[::-1, :], rtol=0, atol=1e-12 * scale)
+        np.testing.assert_allclose(phi, phi.T, rtol=0, atol=1e-12 * scale)
     assert errs[1] < errs[0] and 1.6 < errs[0] / errs[1] < 2.4, errs
+    assert 1.6 < edge[0] / edge[1] < 2.4 and edge[1] < 1.5 * errs[1], (edge, errs)
 
 
 def test_formula_solutions_match_the_viscosity_solution():
