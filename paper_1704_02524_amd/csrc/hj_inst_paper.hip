@@ -57,14 +57,18 @@ hipError_t launch_lax_friedrichs(const PaperProblem& P, double x0, double y0, do
   const int block = 256;
   const int64_t cells = (int64_t)nx * ny;
   const unsigned grid = (unsigned)((cells + block - 1) / block);
-  // an even number of ping-pong steps ends in the array the caller reads
-  double* a = (nt % 2 == 0) ? phi : work;
-  double* b = (nt % 2 == 0) ? work : phi;
+  // kLfT steps per launch; an even number of ping-pong launches ends in the
+  // array the caller reads
+  const int launches = (nt + kLfT - 1) / kLfT;
+  double* a = (launches % 2 == 0) ? phi : work;
+  double* b = (launches % 2 == 0) ? work : phi;
   hipLaunchKernelGGL(k_lf_init, dim3(grid), dim3(block), 0, st, P, x0, y0, dx, dy, nx, ny, a);
   hipError_t e = hipGetLastError();
-  for (int s = 0; s < nt && e == hipSuccess; ++s) {
-    hipLaunchKernelGGL(k_lf_step, dim3(grid), dim3(block), 0, st, P, x0, y0, dx, dy, nx, ny,
-                       dt, ax, ay, a, b);
+  const dim3 tiles((unsigned)((nx + kLfTX - 1) / kLfTX), (unsigned)((ny + kLfTY - 1) / kLfTY));
+  for (int s = 0; s < nt && e == hipSuccess; s += kLfT) {
+    const int nsub = nt - s < kLfT ? nt - s : kLfT;
+    hipLaunchKernelGGL(k_lf_steps, tiles, dim3(block), 0, st, P, x0, y0, dx, dy, nx, ny, dt, ax,
+                       ay, nsub, a, b);
     e = hipGetLastError();
     double* tmp = a;
     a = b;

@@ -458,25 +458,74 @@ __global__ __launch_bounds__(256) void k_lf_init(PaperProblem P, double x0, doub
   phi[c] = paper_g<2>(P, xy);
 }
 
-__global__ __launch_bounds__(256) void k_lf_step(PaperProblem P, double x0, double y0, double dx,
-                                                 double dy, int nx, int ny, double dt,
-                                                 double ax, double ay,
-                                                 const double* __restrict__ old,
-                                                 double* __restrict__ nw) {
-  const int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (cell >= (int64_t)nx * ny) return;
-  const int i = (int)(cell % nx), j = (int)(cell / nx);
-  const double c = old[cell];
-  const double l = i > 0 ? old[cell - 1] : 2.0 * c - old[cell + 1];
-  const double r = i < nx - 1 ? old[cell + 1] : 2.0 * c - old[cell - 1];
-  const double d = j > 0 ? old[cell - nx] : 2.0 * c - old[cell + nx];
-  const double u = j < ny - 1 ? old[cell + nx] : 2.0 * c - old[cell - nx];
-  const double pp = (r - c) / dx, pm = (c - l) / dx;
-  const double qp = (u - c) / dy, qm = (c - d) / dy;
-  const double Hn = lf_hamiltonian(P, x0 + i * dx, y0 + j * dy, 0.5 * (pp + pm),
-                                   0.5 * (qp + qm)) -
+// One Lax-Friedrichs update of a cell from its value c and its four
+// neighbours (left, right, down, up) at the previous level.
+// idx, idy: 1 / dx, 1 / dy.
+__device__ __forceinline__ double lf_update(const PaperProblem& P, double x, double y, double c,
+                                            double l, double r, double d, double u, double idx,
+                                            double idy, double dt, double ax, double ay) {
+  const double pp = (r - c) * idx, pm = (c - l) * idx;
+  const double qp = (u - c) * idy, qm = (c - d) * idy;
+  const double Hn = lf_hamiltonian(P, x, y, 0.5 * (pp + pm), 0.5 * (qp + qm)) -
                     0.5 * ax * (pp - pm) - 0.5 * ay * (qp - qm);
-  nw[cell] = c - dt * Hn;
+  return c - dt * Hn;
+}
+
+// The Lax-Friedrichs solver, several steps per launch (temporal blocking).
+// A block owns a tile of kLfTX x kLfTY cells; it loads the tile with a halo
+// of kLfT cells into LDS, advances the whole region nsub <= kLfT steps
+// there, and writes back its own cells.  Each step's valid region shrinks
+// by one cell on every side that borders another tile's cells; a side on
+// the domain boundary keeps its edge cells, which extrapolate their missing
+// neighbour linearly from the in-tile one.  Every cell takes lf_update
+// whatever the tiling, so the result does not depend on it; the grid makes
+// a round trip through the cache hierarchy, and the device a launch, per
+// kLfT steps instead of per step.  A block's 256 lanes walk a rectangle 4
+// rows of 64 columns at a time (no integer division per cell).
+constexpr int kLfTX = 64, kLfTY = 32, kLfT = 4;
+constexpr int kLfRW = kLfTX + 2 * kLfT, kLfRH = kLfTY + 2 * kLfT;
+
+__global__ __launch_bounds__(256) void k_lf_steps(PaperProblem P, double x0, double y0,
+                                                  double dx, double dy, int nx, int ny,
+                                                  double dt, double ax, double ay, int nsub,
+                                                  const double* __restrict__ in,
+                                                  double* __restrict__ out) {
+  __shared__ double buf[2][kLfRH * kLfRW];
+  // the block walks a rectangle as 4 rows of 64 columns at a time
+  const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+  const double idx = 1.0 / dx, idy = 1.0 / dy;
+  const int tx0 = blockIdx.x * kLfTX, ty0 = blockIdx.y * kLfTY;  // tile origin
+  const int gx0 = tx0 - kLfT, gy0 = ty0 - kLfT;                  // region origin
+  // the region clipped to the domain
+  const int rxl = gx0 > 0 ? gx0 : 0, rxh = gx0 + kLfRW < nx ? gx0 + kLfRW : nx;
+  const int ryl = gy0 > 0 ? gy0 : 0, ryh = gy0 + kLfRH < ny ? gy0 + kLfRH : ny;
+  for (int gy = ryl + tr; gy < ryh; gy += 4)
+    for (int gx = rxl + tc; gx < rxh; gx += 64)
+      buf[0][(gy - gy0) * kLfRW + (gx - gx0)] = in[(int64_t)gy * nx + gx];
+  __syncthreads();
+  int cur = 0;
+  for (int s = 1; s <= nsub; ++s) {
+    const int xl = rxl == 0 ? 0 : rxl + s, xh = rxh == nx ? nx : rxh - s;
+    const int yl = ryl == 0 ? 0 : ryl + s, yh = ryh == ny ? ny : ryh - s;
+    const double* B = buf[cur];
+    double* Nw = buf[cur ^ 1];
+    for (int gy = yl + tr; gy < yh; gy += 4)
+      for (int gx = xl + tc; gx < xh; gx += 64) {
+        const int L = (gy - gy0) * kLfRW + (gx - gx0);
+        const double ce = B[L];
+        const double l = gx > 0 ? B[L - 1] : 2.0 * ce - B[L + 1];
+        const double r = gx < nx - 1 ? B[L + 1] : 2.0 * ce - B[L - 1];
+        const double d = gy > 0 ? B[L - kLfRW] : 2.0 * ce - B[L + kLfRW];
+        const double u = gy < ny - 1 ? B[L + kLfRW] : 2.0 * ce - B[L - kLfRW];
+        Nw[L] = lf_update(P, x0 + gx * dx, y0 + gy * dy, ce, l, r, d, u, idx, idy, dt, ax, ay);
+      }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const int xe = tx0 + kLfTX < nx ? tx0 + kLfTX : nx, ye = ty0 + kLfTY < ny ? ty0 + kLfTY : ny;
+  for (int gy = ty0 + tr; gy < ye; gy += 4)
+    for (int gx = tx0 + tc; gx < xe; gx += 64)
+      out[(int64_t)gy * nx + gx] = buf[cur][(gy - gy0) * kLfRW + (gx - gx0)];
 }
 
 }  // namespace hj
