@@ -432,9 +432,8 @@ __global__ __launch_bounds__(256) void k_eval_paper(PaperProblem P, const double
 // dimensions (the independent check of section 5), H of the quadratic
 // family: phi^{k+1} = phi^k - dt [H(x, (D+x + D-x)/2, (D+y + D-y)/2)
 //   - ax (D+x - D-x)/2 - ay (D+y - D-y)/2], one-sided differences D+-,
-// linear extrapolation across the boundary.  One thread per cell, one launch
-// per time step (reads the old array, writes the new one); row j of phi is
-// y_j = y0 + j dy, column i is x_i = x0 + i dx.
+// linear extrapolation across the boundary; row j of phi is y_j = y0 + j dy,
+// column i is x_i = x0 + i dx.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double lf_hamiltonian(const PaperProblem& P, double x, double y,
                                                  double p1, double p2) {
