@@ -1,13 +1,15 @@
-"""Autotuner for the launch configuration of hj_solve.
+"""Autotuner for the launch configuration of hj_solve and hj_batch_plan.
 
-The tunable knobs do not change results: the lane shape (lanes per task,
-which fixes how many vector components each lane holds) only changes the
-summation order at rounding level, and the adjoint checkpoint interval K
+The tunable knobs do not change results beyond rounding: the lane shape
+(lanes per task, which fixes how many vector components each lane holds)
+only changes the summation order, and the adjoint checkpoint interval K
 changes nothing (the recomputed segments are bit-identical to the forward
-solve).  For a workload the tuner times every candidate on the full point
-set with the iteration cap lowered (so occupancy and per-iteration cost are
-those of the real run), keeps the fastest, and caches the choice in a JSON
-table keyed by the workload's shape.
+solve).  For a single workload the tuner times every lane shape at the
+workload's own checkpoint interval on the full point set with the
+iteration cap lowered (so occupancy and per-iteration cost are those of the
+real run), keeps the fastest, and caches the choice in a JSON table keyed
+by the workload's shape.  For a batch it searches a per-class table on the
+whole plan (tune_batched).
 """
 from __future__ import annotations
 
@@ -107,9 +109,11 @@ def candidates(wl):
             continue
         ks = [None]
         if wl.mode == W.GD_ADJ:
-            # intervals the library would run differently (it caps the
-            # interval of the kernels that recompute segments in LDS)
-            ks = sorted({effective_K(wl, lpt, k) for k in (1, 4, 16, wl.ckpt_K)})
+            # the workload's own checkpoint interval, as the library runs it
+            # (capped for the kernels that recompute segments in LDS); the
+            # interval changes no result, so it is a stated choice of the
+            # configuration rather than a tuning knob here
+            ks = [effective_K(wl, lpt, wl.ckpt_K)]
         for K in ks:
             out.append(dict(lanes_per_task=lpt, **({} if K is None else {"ckpt_K": K})))
     return out
