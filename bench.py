@@ -51,16 +51,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic work per unit (FMA = 2 flops, tanh or a division = 1) for
-# dimension n:
+# Algorithmic work (FMA = 2 flops, tanh or a division = 1), the count the
+# roofline uses: an RK4 stage costs F = 16 n + 4 n^2 [drift] + 12, a step
+# 4 F + 12, a solve N steps; a gradient-descent iteration is the trial
+# evaluation plus, when the step is accepted, one recomputation of the
+# checkpointed trajectory and a vector-Jacobian sweep worth about 1.75
+# solves (3.75 solves in all; 3.1 with drift, whose matrix products dominate
+# both directions alike); a coordinate-descent sweep is 3n solves.
+def method_flops(wl, slot_fwd, slot_bwd):
+    dr = wl.A is not None
+    f_st = 16 * wl.n + (4 * wl.n * wl.n if dr else 0) + 12
+    per_solve = wl.nsteps * (4 * f_st + 12)
+    bwd = 2.1 if dr else 2.75
+    return (float(slot_fwd.sum()) + bwd * float(slot_bwd.sum())) * per_solve
+
+
+# The kernel's own, tighter count, beside it: per dimension n
 #   one RK4 stage of the forward solve:  16 n + 16
 #   one stage of the adjoint sweep:      20 n + 14
 # and with a drift matrix A in addition
 #   forward stage: A gamma and A^T p (2 x 2 n^2) and their four updates (8 n)
-#   adjoint stage: A^T lambda_gamma and A lambda_p (2 x 2 n^2) and 4 n
-# A forward solve is N steps of 4 stages, an adjoint sweep N steps of 4
-# adjoint stages.  Recomputation inside the checkpointed adjoint is not
-# counted: it is overhead of the implementation, not work of the method.
+#   adjoint stage: A^T lambda_gamma and A lambda_p (2 x 2 n^2) and 4 n;
+# the recomputation inside the checkpointed adjoint is not counted.
 def fwd_flops(n, N, drift=False):
     return N * 4 * (16 * n + 16 + ((4 * n * n + 8 * n) if drift else 0))
 
@@ -69,25 +81,10 @@ def adj_flops(n, N, drift=False):
     return N * 4 * (20 * n + 14 + ((4 * n * n + 4 * n) if drift else 0))
 
 
-def algorithmic_flops(wl, slot_fwd, slot_bwd):
+def own_flops(wl, slot_fwd, slot_bwd):
     dr = wl.A is not None
     return float(slot_fwd.sum()) * fwd_flops(wl.n, wl.nsteps, dr) + \
         float(slot_bwd.sum()) * adj_flops(wl.n, wl.nsteps, dr)
-
-
-# The hot-path scope table's own count of the same work, for comparison:
-# a stage costs F = 16 n + 4 n^2 [drift] + 12, a step 4 F + 12, a solve N
-# steps, and a gradient-descent iteration about 3.75 solves (the trial
-# evaluation, one recomputation of the checkpointed trajectory and a
-# vector-Jacobian sweep worth about 1.75 solves; 3.1 with drift, whose
-# matrix products dominate both directions alike).  Unlike the count above
-# it includes the adjoint's recomputation.
-def survey_flops(wl, slot_fwd, slot_bwd):
-    dr = wl.A is not None
-    f_st = 16 * wl.n + (4 * wl.n * wl.n if dr else 0) + 12
-    per_solve = wl.nsteps * (4 * f_st + 12)
-    bwd = 2.1 if dr else 2.75
-    return (float(slot_fwd.sum()) + bwd * float(slot_bwd.sum())) * per_solve
 
 
 def _code_only(text):
@@ -338,17 +335,30 @@ def roofline_of(wl, host, kern_ms, cfg, workload, kernel):
     bound = "mfma" if wl.A is not None else "alu"
     peak = PEAK[(bound, dtype)]
     k_s = float(np.mean(kern_ms)) / 1e3
-    flops = algorithmic_flops(wl, host["slot_fwd"], host["slot_bwd"])
-    flops_sv = survey_flops(wl, host["slot_fwd"], host["slot_bwd"])
-    achieved = flops / k_s / 1e12
+    flops = method_flops(wl, host["slot_fwd"], host["slot_bwd"])
+    flops_own = own_flops(wl, host["slot_fwd"], host["slot_bwd"])
+    return roofline_record(bound, peak, k_s, flops, flops_own, measured_traffic(workload, cfg),
+                           kernel, cfg)
+
+
+METHOD_COUNT = ("RK4 stage 16n + 4n^2 [drift] + 12, step 4 stages + 12, solve N steps, "
+                "GD iteration 3.75 solves (3.1 with drift) incl. the adjoint's recomputation, "
+                "CD sweep 3n solves; FMA = 2, tanh or division = 1")
+OWN_COUNT = ("per evaluation N x 4 x (16n + 16 [+ 4n^2 + 8n drift]), per adjoint sweep "
+             "N x 4 x (20n + 14 [+ 4n^2 + 4n drift]); the adjoint's recomputation excluded")
+
+
+def roofline_record(bound, peak, k_s, flops, flops_own, traffic, kernel, launch):
+    """The roofline object: achieved = the algorithmic flops of one launch
+    (method_flops) over the launch's HIP-event duration; the kernel's own,
+    smaller count (no recomputation) beside it."""
     return {
-        "bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-        "frac": achieved / peak, "traffic": measured_traffic(workload, cfg),
-        "kernel": kernel, "launch": cfg, "kernel_ms": float(np.mean(kern_ms)),
-        "algorithmic_flops_per_launch": flops,
-        "scope_table_count": {"flops_per_launch": flops_sv,
-                              "achieved": flops_sv / k_s / 1e12,
-                              "frac": flops_sv / k_s / 1e12 / peak},
+        "bound": bound, "achieved": flops / k_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+        "frac": flops / k_s / 1e12 / peak, "traffic": traffic,
+        "kernel": kernel, "launch": launch, "kernel_ms": k_s * 1e3,
+        "algorithmic_flops_per_launch": flops, "flop_count": METHOD_COUNT,
+        "own_count": {"flops_per_launch": flops_own, "achieved": flops_own / k_s / 1e12,
+                      "frac": flops_own / k_s / 1e12 / peak, "flop_count": OWN_COUNT},
     }
 
 
@@ -376,7 +386,7 @@ def cd_comparison(wl, host, wall, cd_points, tune_cd):
     cert_cd = int((host_cd["cert"] == 1).sum())
     rate_gd = cert_gd / wall
     rate_cd = cert_cd / wall_cd
-    flops_cd = algorithmic_flops(wcd, host_cd["slot_fwd"], host_cd["slot_bwd"])
+    flops_cd = method_flops(wcd, host_cd["slot_fwd"], host_cd["slot_bwd"])
     return {
         "cd_fd": {
             "points": m, "launch": cfg_cd, "ms_per_step": wall_cd * 1e3,
@@ -581,9 +591,9 @@ def main():
         cfg = {"plan": info, "group_cfg": table}
         n_cert = int(sum((h["cert"] == 1).sum() for h in hosts))
         k_s = float(np.mean(kern)) / 1e3
-        flops = sum(algorithmic_flops(w, h["slot_fwd"], h["slot_bwd"])
+        flops = sum(method_flops(w, h["slot_fwd"], h["slot_bwd"])
                     for w, h in zip(wls, hosts))
-        flops_sv = sum(survey_flops(w, h["slot_fwd"], h["slot_bwd"])
+        flops_own = sum(own_flops(w, h["slot_fwd"], h["slot_bwd"])
                        for w, h in zip(wls, hosts))
         peak = PEAK[("alu", dtype)]
         rec = {
@@ -597,15 +607,9 @@ def main():
                             f"captured graph, {dtype.upper()}",
                 "instances": len(wls), "points": int(sum(w.B for w in wls)), "guesses": wl.G,
                 "certified_points": n_cert},
-            "roofline": {
-                "bound": "alu", "achieved": flops / k_s / 1e12, "peak": peak,
-                "unit": "TFLOP/s", "frac": flops / k_s / 1e12 / peak,
-                "traffic": measured_traffic(args.workload, cfg),
-                "kernel": "k_solve_gd (batched launches of one graph)", "launch": cfg,
-                "kernel_ms": float(np.mean(kern)), "algorithmic_flops_per_launch": flops,
-                "scope_table_count": {"flops_per_launch": flops_sv,
-                                      "achieved": flops_sv / k_s / 1e12,
-                                      "frac": flops_sv / k_s / 1e12 / peak}},
+            "roofline": roofline_record("alu", peak, k_s, flops, flops_own,
+                                        measured_traffic(args.workload, cfg),
+                                        "k_solve_gd (batched launches of one graph)", cfg),
             "tuning": tuning,
         }
     else:
