@@ -217,19 +217,24 @@ constexpr int drift_lds_bytes(int npl, int tsize, bool dr) {
 }
 // A one-wave kernel runs one 256-lane block per CU, so a block may take the
 // whole 160 KiB of LDS.  Beside the drift table it keeps there what a
-// gradient sweep does not touch (the point x, the iterate v and the last
-// gradient: 3 npl values a lane, stashed around the sweep to free
+// gradient sweep reads only on its last line (the point x and the iterate
+// v, and with drift the last gradient: stashed around the sweep to free
 // registers) and the states of the checkpointed trajectory that the sweep
 // recomputes (2 npl values each), which would otherwise go to HBM and back
 // once per step.  The number of segment states that fit, at most 15,
 // bounds the checkpoint interval of these kernels at one more than that
-// (FP64 n = 10 on one lane: 2 states, interval 3; FP64 n = 32 with drift:
-// 2 states, interval 3).  Two-wave kernels, and shapes where not even one
-// state fits beside the stash, keep both in HBM and registers.
-// Host and device both use this function.
+// (FP64 n = 10 on one lane: 3 states, interval 4; FP64 n = 32 with drift:
+// 2 states, interval 3).
+// Two-wave kernels, and shapes where not even one state fits beside the
+// stash, keep both in HBM and registers.  Host and device both use this
+// function.
 constexpr int kLdsBlockBytes = 160 * 1024;
+// values a lane stashes around a sweep: x and v, and with drift the last
+// gradient too (there it measured faster; without drift even, and the LDS
+// is worth more as segment states)
+constexpr int stash_values(int npl, bool dr) { return (dr ? 3 : 2) * npl; }
 constexpr int seg_lds_fit(int npl, int tsize, bool dr) {
-  return (kLdsBlockBytes - drift_lds_bytes(npl, tsize, dr) - 3 * npl * tsize * 256) /
+  return (kLdsBlockBytes - drift_lds_bytes(npl, tsize, dr) - stash_values(npl, dr) * tsize * 256) /
          (2 * npl * tsize * 256);
 }
 constexpr int seg_lds_states(int npl, int lpt, int tsize, bool dr) {
@@ -282,7 +287,7 @@ struct Cfg {
   // waves than they gain.
   static constexpr int kWaves = kernel_waves(NPL, LPT, (int)sizeof(T), DR);
   // segment states held in LDS (0: the segment goes to the global scratch)
-  // and the stash of x, v and the gradient around a sweep (with them)
+  // and the stash of x and v (with drift also the gradient) around a sweep
   static constexpr int kSegLds = seg_lds_states(NPL, LPT, (int)sizeof(T), DR);
   static constexpr bool kStash = kSegLds > 0;
   static_assert(kSegLds == 0 || kWaves == 1, "the LDS plan assumes one block per CU");

@@ -102,11 +102,13 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<typename C0::T> A) {
 }
 
 // The gradient sweep of a descent iteration: gt = d(objective)/dv at v.
-// With C::kStash the point x, the iterate v and the last gradient g wait in
-// LDS while the sweep runs (the sweep reads x and v on its last line only,
-// and g not at all), which frees 3 NPL values of registers for it; every
-// lane reads back what it wrote, so no barrier is needed, and the result is
-// the same bit for bit.
+// With C::kStash the point x and the iterate v wait in LDS while the sweep
+// runs (the sweep reads them on its last line only), and on the matrix-core
+// layout the last gradient as well (the sweep does not read it); that frees
+// their registers for the sweep.  Every lane reads back what it wrote, so
+// no barrier is needed, and the result is the same bit for bit.  (Without
+// drift, parking the gradient too costs one segment state of LDS and
+// measured even.)
 template <class C>
 __device__ __forceinline__ void grad_sweep(const Problem<typename C::T>& P,
                                            const LaneParams<C>& L, typename C::T (&x)[C::NPL],
@@ -118,13 +120,14 @@ __device__ __forceinline__ void grad_sweep(const Problem<typename C::T>& P,
   constexpr int NPL = C::NPL;
   T gx[NPL];
   if constexpr (C::kStash) {
-    __shared__ T s_st[3 * NPL * 256];
+    constexpr bool SG = C::DR;  // the gradient too
+    __shared__ T s_st[(SG ? 3 : 2) * NPL * 256];
     T* const sx = s_st + threadIdx.x;
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       sx[k * 256] = x[k];
       sx[(NPL + k) * 256] = v[k];
-      sx[(2 * NPL + k) * 256] = g[k];
+      if constexpr (SG) sx[(2 * NPL + k) * 256] = g[k];
     }
     // the values now live in LDS only: the compiler may neither keep them
     // in registers across the sweep nor skip the reloads
@@ -138,7 +141,7 @@ __device__ __forceinline__ void grad_sweep(const Problem<typename C::T>& P,
     for (int k = 0; k < NPL; ++k) {
       x[k] = sx[k * 256];
       v[k] = sx[(NPL + k) * 256];
-      g[k] = sx[(2 * NPL + k) * 256];
+      if constexpr (SG) g[k] = sx[(2 * NPL + k) * 256];
       if (P.formula == HJ_HOPF) gt[k] -= x[k];  // as backward's last line
     }
   } else {

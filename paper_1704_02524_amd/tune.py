@@ -78,7 +78,8 @@ def seg_lds_states(npl: int, lpt: int, tsize: int, dr: bool) -> int:
     if not dr and tsize == 4 and (lpt == 16 or npl <= 5):
         return 0
     table = (2 * (npl // 4) * npl * 64 + 4 * npl) * tsize if dr else 0
-    fit = (160 * 1024 - table - 3 * npl * tsize * 256) // (2 * npl * tsize * 256)
+    stash = (3 if dr else 2) * npl
+    fit = (160 * 1024 - table - stash * tsize * 256) // (2 * npl * tsize * 256)
     return 0 if fit < 1 else min(15, fit)
 
 
