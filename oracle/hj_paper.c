@@ -278,9 +278,164 @@ static double lax_residual(const hjp_problem *P, const double *gam, const double
     return r;
 }
 
+/* The staggered discrete schemes of the section 3 lemmas, in the paper's
+ * index n = 0..N with x_N = x, p_N = v and delta = t / N:
+ *   Lax  (eq. hahalolXDform):  p_{n-1} = p_n + delta H_x(x_n, p_n),
+ *                              x_n - x_{n-1} = delta H_p(x_{n-1}, p_{n-1})
+ *        (explicit in p, implicit in x_{n-1});
+ *   Hopf (eq. hahalolXDform2): x_{n-1} = x_n - delta H_p(x_n, p_n),
+ *                              p_{n-1} - p_n = delta H_x(x_{n-1}, p_{n-1})
+ *        (explicit in x, implicit in p_{n-1}; needed for n - 1 >= 1).
+ * The implicit equations are solved by fixed-point iteration from the
+ * explicit guess, to a step below 1e-14 (1 + |z|_inf) or 60 sweeps.
+ * X and Pm hold [(N+1) n] (row n). */
+static void stagger_solve(const hjp_problem *P, const double *rhs0, const double *other,
+                          int implicit_x, double delta, double *z)
+{
+    /* implicit_x: z = rhs0 - delta H_p(z, other)  (Lax, z = x_{n-1})
+     * else:       z = rhs0 + delta H_x(other, z)  (Hopf, z = p_{n-1}) */
+    const int n = P->n;
+    double *w = (double *)malloc(sizeof(double) * 3 * n), *Hx = w, *Hp = w + n, *zn = w + 2 * n;
+    for (int it = 0; it < 60; ++it) {
+        if (implicit_x) {
+            hjp_grads(P, z, other, Hx, Hp);
+            for (int i = 0; i < n; ++i)
+                zn[i] = rhs0[i] - delta * Hp[i];
+        } else {
+            hjp_grads(P, other, z, Hx, Hp);
+            for (int i = 0; i < n; ++i)
+                zn[i] = rhs0[i] + delta * Hx[i];
+        }
+        double dz = 0.0, nz = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double d = fabs(zn[i] - z[i]);
+            if (d > dz || d != d)
+                dz = d;
+            if (fabs(zn[i]) > nz)
+                nz = fabs(zn[i]);
+            z[i] = zn[i];
+        }
+        if (!(dz > 1e-14 * (1.0 + nz)))
+            break;
+    }
+    free(w);
+}
+
+static void staggered(const hjp_problem *P, const double *x, const double *v, double *X,
+                      double *Pm)
+{
+    const int n = P->n, N = P->nsteps;
+    const double delta = P->t / N;
+    double *w = (double *)malloc(sizeof(double) * 2 * n), *Hx = w, *Hp = w + n;
+    memcpy(X + (size_t)N * n, x, sizeof(double) * n);
+    memcpy(Pm + (size_t)N * n, v, sizeof(double) * n);
+    for (int m = N; m >= 1; --m) {
+        double *xm = X + (size_t)m * n, *pm = Pm + (size_t)m * n;
+        double *xl = X + (size_t)(m - 1) * n, *pl = Pm + (size_t)(m - 1) * n;
+        hjp_grads(P, xm, pm, Hx, Hp);
+        if (P->functional != HJP_HOPF) {
+            for (int i = 0; i < n; ++i) {
+                pl[i] = pm[i] + delta * Hx[i];
+                xl[i] = xm[i] - delta * Hp[i];  /* explicit guess */
+            }
+            stagger_solve(P, xm, pl, 1, delta, xl);
+        } else {
+            for (int i = 0; i < n; ++i) {
+                xl[i] = xm[i] - delta * Hp[i];
+                pl[i] = pm[i];                  /* guess (p_0 is not used) */
+            }
+            if (m - 1 >= 1)
+                stagger_solve(P, pm, xl, 0, delta, pl);
+        }
+    }
+    free(w);
+}
+
+/* The staggered functionals and their certificates.
+ *   Lax:  F = g(x_0) + sum_{n=0}^{N-1} <p_n, x_{n+1} - x_n> - delta sum_{n=0}^{N-1} H(x_n, p_n),
+ *         certificate p_{-1} = p_0 + delta H_x(x_0, p_0) = grad g(x_0)
+ *         (stationarity in x_0);
+ *   F2:   min_n g(x_n), certificate at the first minimiser from n = N down;
+ *   Hopf: G = <p_N, x> - g*(p_1) - delta sum_{n=1}^{N} H(x_n, p_n)
+ *             + sum_{n=1}^{N-1} <p_n - p_{n+1}, x_n>, minimised as -G,
+ *         certificate x_0 = grad g*(p_1) (stationarity in p_1). */
+static double stagger_eval(const hjp_problem *P, const double *x, const double *v, double *rho,
+                           double *yN)
+{
+    const int n = P->n, N = P->nsteps;
+    const double delta = P->t / N;
+    double *X = (double *)malloc(sizeof(double) * (size_t)(N + 1) * n);
+    double *Pm = (double *)malloc(sizeof(double) * (size_t)(N + 1) * n);
+    staggered(P, x, v, X, Pm);
+    double phi, r = 0.0;
+    const double *xc, *pc;
+    if (P->functional == HJP_HOPF) {
+        double G = 0.0;
+        for (int i = 0; i < n; ++i)
+            G += Pm[(size_t)N * n + i] * x[i];
+        G -= gstar(P, Pm + n);
+        for (int m = 1; m <= N; ++m)
+            G -= delta * hjp_hamiltonian(P, X + (size_t)m * n, Pm + (size_t)m * n);
+        for (int m = 1; m <= N - 1; ++m)
+            for (int i = 0; i < n; ++i)
+                G += (Pm[(size_t)m * n + i] - Pm[(size_t)(m + 1) * n + i]) * X[(size_t)m * n + i];
+        phi = -G;
+        xc = X;
+        pc = Pm + n;
+        for (int i = 0; i < n; ++i) {
+            double d = fabs(xc[i] - P->a[i] * P->a[i] * pc[i]);
+            if (d > r || d != d)
+                r = d;
+        }
+    } else if (P->functional == HJP_LAX_MIN) {
+        int mb = N;
+        phi = hjp_g(P, X + (size_t)N * n);
+        for (int m = N - 1; m >= 0; --m) {
+            double gm = hjp_g(P, X + (size_t)m * n);
+            if (gm < phi || (gm != gm && phi == phi)) {
+                phi = gm;
+                mb = m;
+            }
+        }
+        xc = X + (size_t)mb * n;
+        pc = Pm + (size_t)mb * n;
+        r = lax_residual(P, xc, pc);
+    } else {
+        phi = hjp_g(P, X);
+        for (int m = 0; m <= N - 1; ++m) {
+            for (int i = 0; i < n; ++i)
+                phi += Pm[(size_t)m * n + i] *
+                       (X[(size_t)(m + 1) * n + i] - X[(size_t)m * n + i]);
+            phi -= delta * hjp_hamiltonian(P, X + (size_t)m * n, Pm + (size_t)m * n);
+        }
+        /* the co-state recursion carried one step past n = 0: its value
+         * p_0 + delta H_x(x_0, p_0) meets grad g(x_0) exactly where F is
+         * stationary in v (the x_0-derivative of the functional) */
+        double *w = (double *)malloc(sizeof(double) * 2 * n), *Hx = w, *Hp = w + n;
+        hjp_grads(P, X, Pm, Hx, Hp);
+        for (int i = 0; i < n; ++i)
+            Pm[i] += delta * Hx[i];
+        free(w);
+        xc = X;
+        pc = Pm;
+        r = lax_residual(P, xc, pc);
+    }
+    if (rho)
+        *rho = r;
+    if (yN) {
+        memcpy(yN, xc, sizeof(double) * n);
+        memcpy(yN + n, pc, sizeof(double) * n);
+    }
+    free(X);
+    free(Pm);
+    return phi;
+}
+
 double hjp_eval(const hjp_problem *P, const double *x, const double *v, double *rho,
                 double *yN)
 {
+    if (P->ode == HJP_STAGGERED)
+        return stagger_eval(P, x, v, rho, yN);
     const int n = P->n, n2 = 2 * n, N = P->nsteps;
     double *traj = (double *)malloc(sizeof(double) * (size_t)(N + 1) * n2);
     double q = trajectory(P, x, v, traj);

@@ -7,6 +7,9 @@
  *    differences for derivatives (eq. num_diff), and Algorithm 1 (section
  *    4.1: cyclic coordinate descent with alpha = 1/L halved every M
  *    coordinate updates, stopped after d consecutive moves below epsilon);
+ *    or the staggered discrete Lax and Hopf forms of the section 3 lemmas
+ *    (eqs. hahalolXDform, hahalolXDform2) in place of Euler and the
+ *    rectangle rule;
  *  - degree-1 homogeneous Hamiltonians (section 5 Examples 3 and 5)
  *        H(x, p) = s1 c1(x) |p_A| + s2 c2(x) |p_B|,
  *        A = {1..k}, B = {k+1..n}, c_i(x) = c0 (1 + beta exp(-gam |x - mu_i|^2)),
@@ -36,7 +39,7 @@ extern "C" {
 enum { HJP_H_QUADRATIC = 0, HJP_H_NORM = 1 };
 enum { HJP_J_ELLIPSOID = 0, HJP_J_ROSENBROCK = 1 };
 enum { HJP_LAX = 0, HJP_HOPF = 1, HJP_LAX_MIN = 2 };   /* F1, G, F2 */
-enum { HJP_RK4 = 0, HJP_EULER = 1 };                    /* ODE + quadrature */
+enum { HJP_RK4 = 0, HJP_EULER = 1, HJP_STAGGERED = 2 };  /* ODE + quadrature */
 enum { HJP_ALG1 = 0, HJP_MOMENTUM = 1 };                /* descent */
 enum { HJP_ST_MAXITER = 0, HJP_ST_CONVERGED = 1, HJP_ST_STALLED = 2, HJP_ST_DIVERGED = 3 };
 

@@ -32,7 +32,7 @@ LAX, HOPF, LAX_MIN = 0, 1, 2          # functionals F1, G, F2 (grid minimum)
 TRAPZ, RK4AUG = 0, 1
 CD_FD, GD_ADJ, ALG1, MOMENTUM = 0, 1, 2, 3
 F64, F32 = 0, 1
-RK4, EULER = 0, 1                     # characteristic ODE scheme
+RK4, EULER, STAGGERED = 0, 1, 2       # characteristic ODE scheme
 H_QUADRATIC, H_NORM = 0, 1
 J_ELLIPSOID, J_ROSENBROCK = 0, 1
 

@@ -37,6 +37,15 @@ MUTANTS = [
  ("certificate direction of grad g", "        unit(n, gg, u2);", "        memcpy(u2, gg, sizeof(double) * n);"),
  ("LF viscosity sign", "hjp_hamiltonian(P, pt, p) - 0.5 * ax * (pp - pm)", "hjp_hamiltonian(P, pt, p) + 0.5 * ax * (pp - pm)"),
  ("LF boundary extrapolation", "double l = i > 0 ? phi[(size_t)j * nx + i - 1] : 2.0 * c - phi[(size_t)j * nx + 1];", "double l = i > 0 ? phi[(size_t)j * nx + i - 1] : phi[(size_t)j * nx + 1];"),
+ ("staggered Lax: no implicit solve for x", "            stagger_solve(P, xm, pl, 1, delta, xl);", "            (void)0;"),
+ ("staggered Hopf: no implicit solve for p", "                stagger_solve(P, pm, xl, 0, delta, pl);", "                (void)0;"),
+ ("staggered Lax: explicit p uses p_{n-1}", "                pl[i] = pm[i] + delta * Hx[i];", "                pl[i] = pm[i] - delta * Hx[i];"),
+ ("staggered Hopf: g* at p_N", "        G -= gstar(P, Pm + n);", "        G -= gstar(P, Pm + (size_t)N * n);"),
+ ("staggered Lax: certificate at p_0", "            Pm[i] += delta * Hx[i];", "            Pm[i] += 0.0 * Hx[i];"),
+ ("staggered Hopf: H sum from 0", "        for (int m = 1; m <= N; ++m)\n            G -= delta", "        for (int m = 0; m <= N; ++m)\n            G -= delta"),
+ ("staggered Hopf: correction sign", "                G += (Pm[(size_t)m * n + i] - Pm[(size_t)(m + 1) * n + i])", "                G += (Pm[(size_t)(m + 1) * n + i] - Pm[(size_t)m * n + i])"),
+ ("staggered Lax: H at x_{n+1}", "            phi -= delta * hjp_hamiltonian(P, X + (size_t)m * n, Pm + (size_t)m * n);", "            phi -= delta * hjp_hamiltonian(P, X + (size_t)(m + 1) * n, Pm + (size_t)m * n);"),
+ ("staggered Hopf: certificate at x_1", "        xc = X;\n        pc = Pm + n;", "        xc = X + n;\n        pc = Pm + n;"),
  ("RK4 stage weight", "q += h / 6.0 * (i1 + 2.0 * i2 + 2.0 * i3 + i4);", "q += h / 6.0 * (i1 + i2 + 2.0 * i3 + 2.0 * i4);"),
 ]
 

@@ -111,6 +111,104 @@ def test_euler_hopf_oscillator_converges_at_first_order(sign):
     assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2, errs
 
 
+def test_staggered_free_particle_lax_is_exact():
+    """The staggered Lax form of the section 3 lemma is exact for H = 1/2|p|^2
+    (p constant, x_n - x_{n-1} = delta p): F(v) = 1/2|x - t v|^2 + t/2|v|^2
+    - 1/2, and Algorithm 1 finds v = x/(1+t), u = |x|^2/(2(1+t)) - 1/2."""
+    wl = _wl(t=0.6, nsteps=7, ode=W.STAGGERED)
+    o = PaperOracle(wl)
+    x = np.array([0.7, -1.3])
+    for v in (np.array([0.1, 0.2]), np.array([-1.0, 0.5])):
+        phi, _, _ = o.eval(x, v)
+        assert phi == pytest.approx(0.5 * np.sum((x - 0.6 * v) ** 2) + 0.3 * v @ v - 0.5,
+                                    abs=1e-14)
+    r = o.descend(x, np.array([1.5, 1.5]))
+    assert r["status"] == 1
+    np.testing.assert_allclose(r["v"], x / 1.6, atol=1e-6)
+    assert r["rho"] < 1e-6
+
+
+def test_staggered_hopf_x_independent_solve_is_exact():
+    """The staggered Hopf form with H = 1/2 sum d p^2 keeps p_n = v and
+    moves x_0 = x - t D v, so G = <x,v> - g*(v) - t/2 sum d v^2 exactly and
+    u = 1/2 sum x^2/(a^2 + t d) + j0 (section 3.4's first example)."""
+    a, d = np.array([1.5, 2.0]), np.array([-1.0, 1.0])
+    wl = _wl(t=0.5, nsteps=9, d=d, a=a, j0=-0.3, formula=W.HOPF, alpha0=1 / 3,
+             fd_sigma=1e-8, eps_step=1e-12, cert_tol=1e-5, ode=W.STAGGERED)
+    x = np.array([[0.8, -1.1], [-0.4, 0.3]])
+    r = PaperOracle(wl).solve(x, np.zeros((2, 1, 1, 2)))
+    assert (r["cert"] == 1).all()
+    np.testing.assert_allclose(r["u"], 0.5 * (x ** 2 / (a ** 2 + 0.5 * d)).sum(1) - 0.3,
+                               atol=1e-6)
+
+
+@pytest.mark.parametrize("sign,formula", [(1, W.HOPF), (-1, W.HOPF), (1, W.LAX)])
+def test_staggered_oscillator_converges_at_first_order(sign, formula):
+    """Example 2's oscillator with the staggered forms (x-dependent H_x, so
+    p and x alternate): the discrete value converges to the closed form at
+    first order in the step, for Hopf (both signs) and Lax (convex H)."""
+    a = np.array([1.0, 2.5])
+    x = np.array([0.8, -1.1])
+    errs = []
+    for N in (20, 40, 80):
+        wl = _wl(t=0.5, nsteps=N, d=np.full(2, float(sign)), w=float(sign), a=a,
+                 formula=formula, alpha0=1 / 3, fd_sigma=1e-8, eps_step=1e-12,
+                 ode=W.STAGGERED)
+        r = PaperOracle(wl).descend(x, np.array([0.2, -0.2]))
+        u = -r["phi"] if formula == W.HOPF else r["phi"]
+        errs.append(abs(u - _osc_exact(x, a, 0.5, sign)))
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3, errs
+
+
+@pytest.mark.parametrize("formula", [W.LAX, W.HOPF])
+def test_staggered_state_dependent_converges_to_the_rk4_value(formula):
+    """With a state-dependent speed (H_p depends on x, so each staggered step
+    solves an implicit equation) the staggered functional at fixed v
+    converges at first order to the continuous one, computed independently
+    by the RK4 reference at a fine step."""
+    from oracle.oracle import Oracle
+    n, t = 3, 0.6
+    d = np.array([-1.0, 1.0, 1.0]) if formula == W.HOPF else np.ones(n)
+    a = np.array([1.8, 1.2, 0.9])
+    kw = dict(m_kind=W.M_TANH, e=1, kappa=0.5, s=float(n), w=0.0, d=d, a=a, j0=-0.5,
+              formula=formula)
+    x = np.array([0.6, -0.4, 0.9])
+    v = np.array([0.3, 0.5, -0.2])
+    ref = Oracle(n=n, t=t, nsteps=800, m_kind=W.M_TANH, e=1, kappa=0.5, s=float(n), w=0.0,
+                 d=d, a=a, j0=-0.5, formula=formula, quad=W.RK4AUG)
+    exact = ref.eval(x, v)[0]
+    errs = []
+    for N in (40, 80, 160):
+        o = PaperOracle(_wl(n=n, t=t, nsteps=N, ode=W.STAGGERED, **kw))
+        errs.append(abs(o.eval(x, v)[0] - exact))
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3, errs
+
+
+@pytest.mark.parametrize("formula", [W.LAX, W.HOPF])
+def test_staggered_dynamics_are_the_stationarity_conditions(formula):
+    """Section 3's lemmas obtain the staggered recursions as the
+    stationarity conditions of the discrete functional in the interior
+    points, so at a critical point of the value as a function of v the
+    remaining end condition holds exactly: grad g(x_0) equals the co-state
+    carried past n = 0 (Lax), grad g*(p_1) equals x_0 (Hopf).  A descent to
+    that critical point, with a state-dependent H (implicit steps), must
+    therefore certify to the descent's accuracy, not to O(delta)."""
+    n = 3
+    d = np.array([-1.0, 1.0, 1.0]) if formula == W.HOPF else np.ones(n)
+    wl = _wl(n=n, t=0.6, nsteps=10, m_kind=W.M_TANH, e=1, kappa=0.5, s=float(n), d=d,
+             a=np.array([1.8, 1.2, 0.9]), formula=formula, ode=W.STAGGERED, alpha0=1 / 3,
+             fd_sigma=1e-8, eps_step=1e-12, M=2000)
+    o = PaperOracle(wl)
+    x = np.array([0.6, -0.4, 0.9])
+    r = o.descend(x, np.zeros(n))
+    assert r["status"] == 1
+    h = 1e-6
+    grad = [(o.eval(x, r["v"] + h * e)[0] - o.eval(x, r["v"] - h * e)[0]) / (2 * h)
+            for e in np.eye(n)]
+    assert np.max(np.abs(grad)) < 1e-6
+    assert r["rho"] < 1e-6
+
+
 def test_rk4_option_converges_at_fourth_order():
     a = np.array([1.0, 2.5])
     x = np.array([0.8, -1.1])
@@ -198,14 +296,15 @@ def test_norm_hamiltonian_derivatives_and_homogeneity():
             assert np.all(Hq[:wl.k_split] == 0.0)
 
 
-def test_huygens_functional_closed_form_ball_minimum():
+@pytest.mark.parametrize("ode", [W.EULER, W.STAGGERED])
+def test_huygens_functional_closed_form_ball_minimum(ode):
     """H = c|p| with constant c: the value is the minimum of g over the ball
     of radius c t (Huygens).  For g = 1/2|x|^2 - 1/2 and |x| > c t it is
     1/2(|x| - c t)^2 - 1/2, reached by v along x at the last grid point, so
     F2's grid minimum is exact; F1 (the sphere only) agrees there, and inside
     the ball (|x| < c t) F2 finds the interior minimum -1/2 where F1 cannot."""
     c, t = 1.5, 0.4
-    wl = _norm_wl(beta=0.0, c0=c, t=t, nsteps=20, formula=W.LAX_MIN)
+    wl = _norm_wl(beta=0.0, c0=c, t=t, nsteps=20, formula=W.LAX_MIN, ode=ode)
     o = PaperOracle(wl)
     x = np.array([1.2, -0.9])
     v = x / np.linalg.norm(x)
@@ -225,14 +324,16 @@ def test_huygens_functional_closed_form_ball_minimum():
     assert phi1 == pytest.approx(0.5 * (c * t - 0.3) ** 2 - 0.5, abs=1e-13)
 
 
-def test_hopf_nonconvex_norm_closed_form():
+@pytest.mark.parametrize("ode", [W.EULER, W.STAGGERED])
+def test_hopf_nonconvex_norm_closed_form(ode):
     """H = c1|p_1| - c2|p_2| with constant c1, c2 and ellipsoid g: the Euler
-    scheme is exact (p constant, integrand equal to H) and the Hopf value is
-    separable: 1/2 max(|x1| - t c1, 0)^2/a1^2 + 1/2 (|x2| + t c2)^2/a2^2 - 1/2."""
+    and the staggered schemes are exact (p constant, integrand equal to H)
+    and the Hopf value is separable: 1/2 max(|x1| - t c1, 0)^2/a1^2 + 1/2
+    (|x2| + t c2)^2/a2^2 - 1/2."""
     t = 0.3  # c1 = c2 = c0 = 1 (beta = 0)
     a = np.array([1.0, 2.5])
     wl = _norm_wl(k_split=1, s1=1.0, s2=-1.0, c0=1.0, beta=0.0, t=t, nsteps=15, a=a,
-                  formula=W.HOPF, fd_sigma=1e-9, eps_step=1e-12, alpha0=0.2)
+                  formula=W.HOPF, fd_sigma=1e-9, eps_step=1e-12, alpha0=0.2, ode=ode)
     o = PaperOracle(wl)
     x = np.array([1.4, -0.7])
     exact = 0.5 * max(abs(x[0]) - t, 0) ** 2 / a[0] ** 2 + \
