@@ -96,9 +96,15 @@ enum { HJ_TRAPZ = 0, HJ_RK4AUG = 1 };     /* trapezoid on the RK4 nodes, or
  * (v' = v - alpha g + momentum (v - v_prev), a rising trial rejected with
  * the momentum dropped and alpha halved) */
 enum { HJ_CD_FD = 0, HJ_GD_ADJ = 1, HJ_ALG1 = 2, HJ_MOMENTUM = 3 };
-/* characteristic ODE: classical RK4, or forward Euler with the rectangle
- * rule h sum_{k<N} integrand(y_k) (section 4.2, eq. num_int) */
-enum { HJ_RK4 = 0, HJ_EULER = 1 };
+/* characteristic ODE: classical RK4, forward Euler with the rectangle
+ * rule h sum_{k<N} integrand(y_k) (section 4.2, eq. num_int), or the
+ * staggered discrete forms of the section 3 lemmas (eqs. hahalolXDform and
+ * hahalolXDform2: one half of each step explicit, the other implicit and
+ * solved by fixed-point iteration to 1e-14 (1 + |z|) or 60 sweeps; the
+ * value is the discrete functional itself, and the Lax certificate compares
+ * grad g(x_0) with p_0 + delta H_x(x_0, p_0), the Hopf one x_0 with
+ * a^2 p_1) */
+enum { HJ_RK4 = 0, HJ_EULER = 1, HJ_STAGGERED = 2 };
 enum { HJ_F64 = 0, HJ_F32 = 1 };
 /* stop status of one descent run */
 enum { HJ_ST_MAXITER = 0, HJ_ST_CONVERGED = 1, HJ_ST_STALLED = 2, HJ_ST_DIVERGED = 3 };
@@ -177,7 +183,7 @@ typedef struct {
                              restarts from its remaining guesses -- in a
                              second launch over the handed-off slots only.
                              0: the FP32 attempts alone decide.            */
-    int32_t ode;          /* HJ_RK4 or HJ_EULER                            */
+    int32_t ode;          /* HJ_RK4, HJ_EULER or HJ_STAGGERED              */
     int32_t M;            /* HJ_ALG1: alpha halves every M updates (>= 1)  */
     double  momentum;     /* HJ_MOMENTUM: the heavy-ball coefficient       */
     /* hj_batch_plan only: launch choices by dimension class (NULL: the
@@ -229,7 +235,8 @@ typedef struct {
 
 /* The paper's scheme and families run in a kernel of their own: a solve
  * with mode HJ_ALG1 or HJ_MOMENTUM (the only modes for HJ_H_NORM,
- * HJ_J_ROSENBROCK, HJ_LAX_MIN or HJ_EULER) takes FP64, no drift matrix,
+ * HJ_J_ROSENBROCK, HJ_LAX_MIN, HJ_EULER or HJ_STAGGERED) takes FP64, no
+ * drift matrix,
  * n <= 16, one lane per (point, guess) (lanes_per_task and the schedule are
  * ignored) and the RK4-augmented rule with HJ_RK4; other combinations are
  * HJ_EUNSUPPORTED.  hj_eval evaluates these functionals without gradients. */

@@ -799,7 +799,8 @@ int check_opts(const hj_opts* o) {
   if (o->dtype != HJ_F64 && o->dtype != HJ_F32) return fail(HJ_EDTYPE, "unknown dtype");
   if (o->formula < HJ_LAX || o->formula > HJ_LAX_MIN) return fail(HJ_EINVAL, "bad formula");
   if (o->mode < HJ_CD_FD || o->mode > HJ_MOMENTUM) return fail(HJ_EINVAL, "bad mode");
-  if (o->ode != HJ_RK4 && o->ode != HJ_EULER) return fail(HJ_EINVAL, "bad ode scheme");
+  if (o->ode != HJ_RK4 && o->ode != HJ_EULER && o->ode != HJ_STAGGERED)
+    return fail(HJ_EINVAL, "bad ode scheme");
   if (o->mode == HJ_ALG1 && o->M < 1) return fail(HJ_EINVAL, "M must be >= 1");
   if ((o->mode == HJ_ALG1 || o->mode == HJ_MOMENTUM) && !(o->fd_sigma > 0.0))
     return fail(HJ_EINVAL, "fd_sigma must be > 0");
@@ -832,14 +833,15 @@ int check_opts(const hj_opts* o) {
 // ---------------------------------------------------------------------------
 bool needs_paper(int H_kind, int J_kind, const hj_opts* o) {
   return o->mode == HJ_ALG1 || o->mode == HJ_MOMENTUM || H_kind == HJ_H_NORM ||
-         J_kind == HJ_J_ROSENBROCK || o->formula == HJ_LAX_MIN || o->ode == HJ_EULER;
+         J_kind == HJ_J_ROSENBROCK || o->formula == HJ_LAX_MIN || o->ode != HJ_RK4;
 }
 
 int check_paper(int H_kind, const hj_h_params* H, int J_kind, int n, const hj_opts* o,
                 bool solve) {
   if (solve && o->mode != HJ_ALG1 && o->mode != HJ_MOMENTUM)
     return fail(HJ_EUNSUPPORTED, "these Hamiltonians, initial data, functionals and the "
-                                 "Euler scheme descend with HJ_ALG1 or HJ_MOMENTUM");
+                                 "Euler and staggered schemes descend with HJ_ALG1 or "
+                                 "HJ_MOMENTUM");
   if (o->dtype != HJ_F64) return fail(HJ_EUNSUPPORTED, "the paper's scheme runs in FP64");
   if (H_kind == HJ_H_QUADRATIC && H->A)
     return fail(HJ_EUNSUPPORTED, "the paper's scheme takes no drift matrix");

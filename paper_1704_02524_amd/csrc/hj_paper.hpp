@@ -1,6 +1,8 @@
 // hj_paper.hpp -- the paper's own scheme and its further problem families on
 // gfx950: forward Euler characteristics with the rectangle rule (section
-// 4.2, eq. num_int) or RK4 with the RK4-augmented rule, forward-difference
+// 4.2, eq. num_int), the staggered discrete Lax and Hopf forms of section 3
+// (implicit half-steps by fixed-point iteration) or RK4 with the
+// RK4-augmented rule, forward-difference
 // derivatives (eq. num_diff) driving Algorithm 1 (section 4.1: cyclic
 // coordinate descent, alpha = 1/L halved every M updates, stopped after d
 // consecutive moves below epsilon) or heavy-ball descent, for
@@ -149,10 +151,134 @@ __device__ __forceinline__ double paper_lax_residual(const PaperProblem& P,
   return r;
 }
 
+// One implicit half-step of the staggered schemes, solved by fixed-point
+// iteration from z (its initial guess) until a sweep moves z by at most
+// 1e-14 (1 + |z|) in the max norm, or for 60 sweeps:
+//   IX (Lax):   z = rhs - delta H_p(z, o), the new x with the new p = o;
+//   else (Hopf): z = rhs + delta H_x(o, z), the new p at the new x = o.
+template <int NPL, int HK, bool IX>
+__device__ __forceinline__ void stagger_fixed_point(const PaperProblem& P,
+                                                    const double (&rhs)[NPL],
+                                                    const double (&o)[NPL], double (&z)[NPL]) {
+  double Hx[NPL], Hp[NPL];
+  for (int it = 0; it < 60; ++it) {
+    if constexpr (IX)
+      paper_grads<NPL, HK>(P, z, o, Hx, Hp);
+    else
+      paper_grads<NPL, HK>(P, o, z, Hx, Hp);
+    double dz = 0.0, nz = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const double zn = IX ? rhs[i] - P.h * Hp[i] : rhs[i] + P.h * Hx[i];
+      dz = nanmax(dz, dabs(zn - z[i]));
+      nz = dabs(zn) > nz ? dabs(zn) : nz;
+      z[i] = zn;
+    }
+    if (!(dz > 1e-14 * (1.0 + nz))) break;
+  }
+}
+
+// The staggered discrete functionals of section 3 (eqs. hahalolXDform and
+// hahalolXDform2), evaluated on the fly from n = N (x_N = x, p_N = v) down
+// to n = 0 with delta = t / N:
+//   Lax dynamics: p_{n-1} = p_n + delta H_x(x_n, p_n), then x_{n-1} from
+//     x_n - x_{n-1} = delta H_p(x_{n-1}, p_{n-1});
+//     F1 = g(x_0) + sum_{n<N} (<p_n, x_{n+1} - x_n> - delta H(x_n, p_n)),
+//     certified by grad g(x_0) = p_0 + delta H_x(x_0, p_0) (stationarity in
+//     x_0); F2 = min over n of g(x_n), first minimiser from n = N down;
+//   Hopf dynamics: x_{n-1} = x_n - delta H_p(x_n, p_n), then for n - 1 >= 1
+//     p_{n-1} from p_{n-1} - p_n = delta H_x(x_{n-1}, p_{n-1});
+//     -G = g*(p_1) - <x, v> + delta sum_{n>=1} H(x_n, p_n)
+//          - sum_{1<=n<N} <p_n - p_{n+1}, x_n>, certified by x_0 = a^2 p_1.
+// Every grads evaluation at a node (x_n, p_n) serves both its H term and the
+// explicit half of the next step.
+template <int NPL, int HK>
+__device__ double paper_stagger_eval(const PaperProblem& P, const double (&x0)[NPL],
+                                     const double (&v)[NPL], double& rho) {
+  double x[NPL], p[NPL], Hx[NPL], Hp[NPL], rhs[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    x[i] = x0[i];
+    p[i] = v[i];
+  }
+  const double h = P.h;
+  double q = 0.0;
+  if (P.functional == HJ_HOPF) {
+    for (int m = P.N; m >= 1; --m) {
+      const double H = paper_grads<NPL, HK>(P, x, p, Hx, Hp);
+      q = fmaT(h, H, q);
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) x[i] = x[i] - h * Hp[i];
+      if (m >= 2) {
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) rhs[i] = p[i];
+        stagger_fixed_point<NPL, HK, false>(P, rhs, x, p);
+        // -<p_{m-1} - p_m, x_{m-1}>
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) q -= (p[i] - rhs[i]) * x[i];
+      }
+    }
+    double gs = 0.0, xv = 0.0, r = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      gs = fmaT(P.a2[i] * p[i], p[i], gs);
+      xv = fmaT(x0[i], v[i], xv);
+      r = nanmax(r, dabs(x[i] - P.a2[i] * p[i]));
+    }
+    rho = r;
+    return 0.5 * gs - P.j0 - xv + q;
+  }
+  const bool fmin = P.functional == HJ_LAX_MIN;
+  double gmin = 0.0, xm[NPL], pm[NPL];
+  if (fmin) {
+    gmin = paper_g<NPL>(P, x);
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      xm[i] = x[i];
+      pm[i] = p[i];
+    }
+  }
+  for (int m = P.N; m >= 1; --m) {
+    const double H = paper_grads<NPL, HK>(P, x, p, Hx, Hp);
+    if (m < P.N) q = fmaT(-h, H, q);  // the H term of node m < N
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      rhs[i] = x[i];
+      p[i] = p[i] + h * Hx[i];
+      x[i] = x[i] - h * Hp[i];
+    }
+    stagger_fixed_point<NPL, HK, true>(P, rhs, p, x);
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) q = fmaT(p[i], rhs[i] - x[i], q);
+    if (fmin) {
+      const double gk = paper_g<NPL>(P, x);
+      if (gk < gmin || (gk != gk && gmin == gmin)) {
+        gmin = gk;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+          xm[i] = x[i];
+          pm[i] = p[i];
+        }
+      }
+    }
+  }
+  if (fmin) {
+    rho = paper_lax_residual<NPL, HK>(P, xm, pm);
+    return gmin;
+  }
+  const double H0 = paper_grads<NPL, HK>(P, x, p, Hx, Hp);
+  q = fmaT(-h, H0, q);
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) p[i] = p[i] + h * Hx[i];
+  rho = paper_lax_residual<NPL, HK>(P, x, p);
+  return paper_g<NPL>(P, x) + q;
+}
+
 // The discrete functional at v (F1, G or F2) and its certificate residual.
 template <int NPL, int HK>
 __device__ double paper_eval(const PaperProblem& P, const double (&x0)[NPL],
                              const double (&v)[NPL], double& rho) {
+  if (P.ode == HJ_STAGGERED) return paper_stagger_eval<NPL, HK>(P, x0, v, rho);
   double x[NPL], p[NPL], Hx[NPL], Hp[NPL];
 #pragma unroll
   for (int i = 0; i < NPL; ++i) {

