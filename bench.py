@@ -134,6 +134,43 @@ def measured_traffic(workload, launch):
     return None
 
 
+def phase_record(wl, host, launch, workload):
+    """Executed instructions of the dominant kernel traced to its phases:
+    instructions per step of the forward, recompute and reverse loops (static
+    counts from the kernel's assembly, profiles/isa_phases_<workload>.md,
+    used only while the kernel-source digest matches) times the steps the
+    launch executed in each phase (lane-steps, from the per-slot forward and
+    adjoint counts), beside each phase's algorithmic flops per step."""
+    path = os.path.join(ROOT, "profiles", f"isa_phases_{workload}.md")
+    try:
+        with open(path) as f:
+            e = json.loads(f.read().split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if e.get("source_digest") != source_digest() or wl.A is not None:
+        return None
+    N, n = wl.nsteps, wl.n
+    K = int(launch.get("ckpt_K", 0) or 0)
+    if K < 1 or e.get("lpt") != launch.get("lanes_per_task"):
+        return None
+    fwd, bwd = float(host["slot_fwd"].sum()), float(host["slot_bwd"].sum())
+    step = 4 * (16 * n + 12) + 12
+    steps = {"forward": fwd * N, "recompute": bwd * (N - (N + K - 1) // K),
+             "reverse": bwd * N}
+    alg = {"forward": step, "recompute": step, "reverse": 1.75 * step}
+    valu = {k: sum(e["phases"][k][c] for c in ("fp64", "agpr", "valu_other")) for k in steps}
+    lane_valu = {k: steps[k] * valu[k] for k in steps}
+    tot = sum(lane_valu.values())
+    out = {"source": "instructions per step from the kernel's assembly x lane-steps executed",
+           "launch_lane_valu": tot}
+    for k in steps:
+        out[k] = {"lane_steps": steps[k], "valu_per_step": valu[k],
+                  "fp64_per_step": e["phases"][k]["fp64"],
+                  "agpr_moves_per_step": e["phases"][k]["agpr"],
+                  "method_flops_per_step": alg[k], "valu_share": lane_valu[k] / tot}
+    return out
+
+
 def _events(k):
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -337,8 +374,12 @@ def roofline_of(wl, host, kern_ms, cfg, workload, kernel):
     k_s = float(np.mean(kern_ms)) / 1e3
     flops = method_flops(wl, host["slot_fwd"], host["slot_bwd"])
     flops_own = own_flops(wl, host["slot_fwd"], host["slot_bwd"])
-    return roofline_record(bound, peak, k_s, flops, flops_own, measured_traffic(workload, cfg),
-                           kernel, cfg)
+    rec = roofline_record(bound, peak, k_s, flops, flops_own, measured_traffic(workload, cfg),
+                          kernel, cfg)
+    ph = phase_record(wl, host, cfg, workload)
+    if ph is not None:
+        rec["phases"] = ph
+    return rec
 
 
 METHOD_COUNT = ("RK4 stage 16n + 4n^2 [drift] + 12, step 4 stages + 12, solve N steps, "

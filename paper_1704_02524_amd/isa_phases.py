@@ -1,0 +1,197 @@
+"""Instructions per step of each phase of a compiled descent kernel.
+
+Compiles one kernel-instantiation source to gfx950 assembly with the
+library's own flags (build.py), finds the adjoint descent kernel of the
+requested lane shape and reads its loop nest from the loop comments the
+compiler writes beside each basic block:
+
+  descent iteration loop
+    forward solve:  one RK4 step (+ quadrature, checkpoint store) per pass
+    adjoint sweep:  one segment per pass, holding
+      recompute:    one RK4 step of the segment from its checkpoint
+      reverse:      one reverse RK4 step (stage vector-Jacobian products)
+
+and counts the instructions of each phase's loop body by class (FP64
+arithmetic, AGPR moves, other vector, scalar, LDS, global and scratch
+memory).  Blocks a pass may skip (the checkpoint store of every K-th
+forward step, rare branches) are included, so the counts are those of the
+longest pass.  Multiplied by the steps a launch executes per phase, they
+trace the executed instructions of the launch to its phases.
+
+    python -m paper_1704_02524_amd.isa_phases --source hj_inst_f64_1.hip \
+        --npl 10 --lpt 1 --mk 2 [--markdown out.md]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import os
+import re
+import subprocess
+
+from paper_1704_02524_amd import build as B
+
+CLASSES = ("fp64", "agpr", "valu_other", "salu", "lds", "global", "scratch", "other")
+
+
+def op_class(op: str) -> str:
+    if op.startswith("v_accvgpr"):
+        return "agpr"
+    if op.startswith("v_") and "_f64" in op:
+        return "fp64"
+    if op.startswith("v_"):
+        return "valu_other"
+    if op.startswith("s_"):
+        return "salu"
+    if op.startswith("ds_"):
+        return "lds"
+    if op.startswith(("global_", "buffer_", "flat_")):
+        return "global"
+    if op.startswith("scratch_"):
+        return "scratch"
+    return "other"
+
+
+def assemble(source: str) -> str:
+    """gfx950 device assembly of one instantiation source (library flags)."""
+    os.makedirs(B.BUILD, exist_ok=True)
+    out = os.path.join(B.BUILD, os.path.splitext(source)[0] + ".s")
+    cmd = [B.HIPCC, *B.FLAGS, *B.PER_SOURCE.get(source, []), "--cuda-device-only", "-S",
+           os.path.join(B.CSRC, source), "-o", out]
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+    return out
+
+
+def kernel_symbol(npl: int, lpt: int, mk: int) -> str:
+    """Mangled name of k_solve_gd for one instance, double, no drift."""
+    return (f"_ZN2hj10k_solve_gdINS_3CfgIdLi{npl}ELi{lpt}ELi{mk}ELb0ELb0EEELb0EEEv"
+            "NS_9SolveArgsINT_1TEEE")
+
+
+def parse(asm_path: str, symbol: str):
+    """Basic blocks of one function: label, innermost loop header, the loop
+    tree (header -> parent, depth), instruction classes per block."""
+    lines = open(asm_path).read().split("\n")
+    start = next(i for i, l in enumerate(lines) if l.startswith(symbol + ":"))
+    end = next(i for i in range(start, len(lines)) if lines[i].strip().startswith(".Lfunc_end"))
+    blocks, loops = [], {}
+    cur = {"label": "entry", "loop": None, "ops": []}
+    i = start + 1
+    while i < end:
+        line = lines[i]
+        m = re.match(r"^(\.LBB\d+_\d+|; %bb\.\d+):?(.*)$", line)
+        if m:
+            blocks.append(cur)
+            label = m.group(1).lstrip(".").replace("LBB", "BB")
+            comments = [m.group(2)]
+            while i + 1 < end and lines[i + 1].strip().startswith(";"):
+                i += 1
+                comments.append(lines[i])
+            text = " ".join(comments)
+            loop = None
+            h = re.search(r"Loop Header: Depth=(\d+)", text)
+            if h:
+                parents = re.findall(r"Parent Loop (BB\d+_\d+) Depth=\d+", text)
+                loops[label] = {"parent": parents[-1] if parents else None,
+                                "depth": int(h.group(1))}
+                loop = label
+            else:
+                h = re.search(r"in Loop: Header=(BB\d+_\d+) Depth=(\d+)", text)
+                if h:
+                    loop = h.group(1)
+            cur = {"label": label, "loop": loop, "ops": []}
+        else:
+            s = line.strip()
+            if s and not s.startswith((";", ".")):
+                cur["ops"].append(s.split()[0])
+        i += 1
+    blocks.append(cur)
+    return blocks, loops
+
+
+def phases(blocks, loops):
+    """The forward, recompute and reverse loops of the descent kernel."""
+    own = collections.defaultdict(collections.Counter)
+    order = []
+    for b in blocks:
+        if b["loop"]:
+            if b["loop"] not in order:
+                order.append(b["loop"])
+            own[b["loop"]].update(op_class(op) for op in b["ops"])
+    children = collections.defaultdict(list)
+    for h, info in loops.items():
+        if info["parent"]:
+            children[info["parent"]].append(h)
+    # the descent iteration loop: the outermost loop holding the most code
+    top = max((h for h in loops if loops[h]["depth"] == 1),
+              key=lambda h: sum(sum(own[c].values()) for c in _subtree(h, children)))
+    inner = [h for h in order if loops.get(h, {}).get("parent") == top]
+    seg = [h for h in inner if children[h]]
+    leaf = [h for h in inner if not children[h]]
+    if len(seg) != 1 or not leaf:
+        raise RuntimeError("unexpected loop nest: %s" % {h: loops[h] for h in loops})
+    fwd = max(leaf, key=lambda h: own[h]["fp64"])
+    rec, rev = [h for h in order if h in children[seg[0]]][:2]
+    return {"forward": own[fwd], "recompute": own[rec], "reverse": own[rev]}
+
+
+def _subtree(h, children):
+    out = [h]
+    for c in children[h]:
+        out += _subtree(c, children)
+    return out
+
+
+def count(source: str, npl: int, lpt: int, mk: int) -> dict:
+    asm = assemble(source)
+    blocks, loops = parse(asm, kernel_symbol(npl, lpt, mk))
+    ph = phases(blocks, loops)
+    return {k: {c: int(v.get(c, 0)) for c in CLASSES} | {"total": int(sum(v.values()))}
+            for k, v in ph.items()}
+
+
+def markdown(res: dict, args, digest: str) -> str:
+    cmd = (f"python -m paper_1704_02524_amd.isa_phases --source {args.source} --npl {args.npl} "
+           f"--lpt {args.lpt} --mk {args.mk} --markdown {args.markdown}")
+    rows = ["| phase | " + " | ".join(CLASSES) + " | total |",
+            "|---|" + "---|" * (len(CLASSES) + 1)]
+    for k, v in res.items():
+        rows.append(f"| {k} | " + " | ".join(str(v[c]) for c in CLASSES) + f" | {v['total']} |")
+    rec = {"source_digest": digest, "npl": args.npl, "lpt": args.lpt, "mk": args.mk, "phases": res}
+    return "\n".join([
+        f"# Instructions per step of each phase: `k_solve_gd` FP64 {args.npl}x{args.lpt}",
+        "",
+        "Static counts from the gfx950 assembly of the library's own build (wave instructions of one",
+        "pass of each phase's loop body, skippable blocks included).  Command (repository root):",
+        "",
+        f"    {cmd}",
+        "",
+        *rows,
+        "",
+        "Machine-readable copy:",
+        "",
+        "```json",
+        json.dumps(rec, indent=1),
+        "```",
+        ""])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--source", default="hj_inst_f64_1.hip")
+    ap.add_argument("--npl", type=int, default=10)
+    ap.add_argument("--lpt", type=int, default=1)
+    ap.add_argument("--mk", type=int, default=2)
+    ap.add_argument("--markdown")
+    args = ap.parse_args()
+    res = count(args.source, args.npl, args.lpt, args.mk)
+    print(json.dumps(res, indent=1))
+    if args.markdown:
+        import bench
+        with open(args.markdown, "w") as fh:
+            fh.write(markdown(res, args, bench.source_digest()))
+
+
+if __name__ == "__main__":
+    main()
