@@ -473,6 +473,11 @@ def paper_examples(grid):
         W.paper_ex3(1, n=2, t=0.3, grid=grid), W.paper_ex3(-1, n=2, t=0.5, grid=grid),
         W.paper_ex3(-1, n=10, t=0.4, grid=grid), W.paper_ex5(n=2, t=0.3, grid=grid),
         W.paper_ex5(n=7, t=0.3, grid=grid),
+    ] + [
+        # the staggered discrete forms of section 3 on the same examples
+        w.with_(name=w.name + "_staggered", ode=W.STAGGERED) for w in (
+            W.paper_ex2(-1, n=2, t=0.5, grid=grid), W.paper_ex2_rosenbrock(grid=grid),
+            W.paper_ex3(1, n=2, t=0.3, grid=grid), W.paper_ex5(n=2, t=0.3, grid=grid))
     ]
 
 
@@ -489,7 +494,8 @@ def bench_paper(args):
         # algorithmic work: every objective evaluation is one solve of N
         # steps; a step costs one H / H_x / H_p evaluation and the integrand
         # (about 12 n flops for the quadratic family, 20 n + an exp pair for
-        # the degree-1 one) and the Euler update (4 n)
+        # the degree-1 one) and the Euler update (4 n); the fixed-point
+        # sweeps of the staggered forms' implicit half-steps are not counted
         per_step = (16 if wl.h_kind == 0 else 24) * wl.n + 12
         flops = evals * wl.nsteps * per_step
         k_s = float(np.mean(kern)) / 1e3
@@ -512,7 +518,8 @@ def bench_paper(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"paper: section 5 examples with the paper's scheme (forward "
                                f"Euler, rectangle rule, forward differences, Algorithm 1, "
-                               f"M = 500, eps = 0.5e-7), {grid}x{grid} cross-section grid on "
+                               f"M = 500, eps = 0.5e-7; four examples also with the staggered "
+                               f"forms of section 3), {grid}x{grid} cross-section grid on "
                                f"[-3,3]^2, U[-2,2] guesses; value: Example 2 H-, d = 2",
                    "examples": rows},
         "roofline": {"bound": "alu", "achieved": head["achieved_tflops"], "peak": peak,
