@@ -122,3 +122,23 @@ def test_paper_errors_are_reported(hj):
     r = W.paper_ex2_rosenbrock(grid=2)
     with pytest.raises(hj.HJError, match="conjugate"):
         hj.solve(r.with_(formula=W.HOPF), *hj.device_inputs(r))
+
+
+@pytest.mark.parametrize("ode", [W.EULER, W.STAGGERED], ids=["euler", "staggered"])
+def test_paper_fullsize_sampled(hj, ode):
+    """The benchmarked paper workload (Example 2 H-, d = 2, 64 x 64 grid
+    points, five guesses each) in the launch the bench times: sampled
+    points, the corners and the centre of the grid among them, recomputed
+    one by one by the reference."""
+    wl = W.paper_ex2(-1, n=2, t=0.5, grid=64).with_(ode=ode)
+    res = hj.solve(wl, *hj.device_inputs(wl))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in res.items()}
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([[0, 63, 2016, 2080, 4032, 4095],
+                                    rng.choice(wl.B, 10, replace=False)]))
+    ref = PaperOracle(wl).solve(wl.x[idx], wl.guesses[idx])
+    np.testing.assert_array_equal(got["cert"][idx], ref["cert"])
+    err = np.abs(got["u"][idx] - ref["u"]) / np.maximum(1, np.abs(ref["u"]))
+    assert err.max() <= 1e-9, err.max()
+    assert (got["cert"] == 1).all()
