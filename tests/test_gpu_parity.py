@@ -92,13 +92,22 @@ def test_eval_matches_reference_fp32(hj, n):
     out = hj.evaluate(wl, _dev(wl.x, wl), _dev(v, wl), grad=True, ckpt_K=8)
     torch.cuda.synchronize()
     o = Oracle.from_workload(wl)
+    # FP32 rounding of the adjoint sweep: 4 N stage products, each rounding
+    # a length-n reduction, so about 4 N sqrt(n) single-precision units of
+    # the gradient's scale (a random-walk accumulation per stage, linear
+    # over the steps)
+    tol = 4 * wl.nsteps * np.sqrt(n) * np.finfo(np.float32).eps
+    worst = 0.0
     for b in range(wl.B):
         for g in range(wl.G):
             phi, _ = o.eval(wl.x[b], v[b, g])
             _, gv, _ = o.grad_tangent(wl.x[b], v[b, g])
             assert abs(out["phi"][b, g].item() - phi) <= 1e-4 * max(1.0, abs(phi))
-            np.testing.assert_allclose(out["grad_v"][b, g].cpu().numpy(), gv, rtol=0,
-                                       atol=1e-3 * max(1.0, np.abs(gv).max()))
+            scale = max(1.0, np.abs(gv).max())
+            err = np.abs(out["grad_v"][b, g].cpu().numpy() - gv).max() / scale
+            worst = max(worst, err)
+            assert err <= tol, (b, g, err, tol)
+    print(f"n={n}: FP32 gradient error {worst:.2e} of its scale (bar {tol:.2e})")
 
 
 @pytest.mark.parametrize("n,lpts,dtype", [(10, [1, 2, 4], W.F64), (3, [1, 2, 4], W.F64),
