@@ -196,6 +196,20 @@ typedef struct {
      * shape's padded dimension; the continuation runs few, long tasks, so
      * more lanes per task shorten them.  HJ_EUNSUPPORTED if not compiled. */
     int32_t cont_lanes_per_task;
+    /* hj_solve, FP64 adjoint descent (HJ_GD_ADJ) of one problem without a
+     * drift matrix: a slot still descending after tail_budget objective
+     * evaluations (0: never) is handed, with its whole descent state (v,
+     * gradient, step size, iteration and attempt counts, best attempt), to
+     * a second launch of tail_lanes_per_task lanes per task (0: 2), which
+     * resumes it exactly where it stopped.  The slow tail of the slots then
+     * runs on wider lane groups instead of holding a one-lane wave for the
+     * whole launch.  Results equal those without the hand-off up to the
+     * rounding of the wider shape's sums (bit for bit with the descent's own
+     * lanes per task).  The tail shape must have the descent shape's padded
+     * dimension and at most 4 lanes per task; HJ_EUNSUPPORTED otherwise, for
+     * FP32, other descent modes, drift and batch plans. */
+    int32_t tail_budget;
+    int32_t tail_lanes_per_task;
 } hj_opts;
 
 /* Launch choices of the instances up to a dimension (an autotuner's table):

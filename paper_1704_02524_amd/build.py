@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libhj.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = (["hj_api.hip"] + [f"hj_inst_{t}_{i}.hip" for t in ("f64", "f32") for i in range(5)]
-           + [f"hj_inst_c64_{i}.hip" for i in range(4)] + ["hj_inst_paper.hip"])
+           + [f"hj_inst_c64_{i}.hip" for i in range(4)] + [f"hj_inst_r64_{i}.hip" for i in range(3)]
+           + ["hj_inst_paper.hip"])
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -36,7 +37,8 @@ FLAGS = [
 # target's own register-pressure trackers (n=10 solve 177 -> 166 ms measured).
 ILP_FLAGS = ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-mllvm", "-amdgpu-use-amdgpu-trackers=1"]
 PER_SOURCE = {src: ILP_FLAGS for src in
-              [f"hj_inst_f64_{i}.hip" for i in range(4)] + [f"hj_inst_c64_{i}.hip" for i in range(3)]}
+              [f"hj_inst_f64_{i}.hip" for i in range(4)] + [f"hj_inst_c64_{i}.hip" for i in range(3)]
+              + [f"hj_inst_r64_{i}.hip" for i in range(3)]}
 
 
 def _compile(src: str, extra=()) -> str:

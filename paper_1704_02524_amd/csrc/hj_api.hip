@@ -171,13 +171,17 @@ struct WsLayout {
   // FP64 continuation of FP32 slots: hand-off list, its counters (entries,
   // continuation queue), FP64 checkpoints over stride64 lanes
   size_t handoff = 0, cont_ctr = 0, ck64 = 0, seg64 = 0, stride64 = 0;
+  // FP64 tail hand-off: the records (the continuation uses cont_ctr and the
+  // ck64 / seg64 checkpoints above)
+  size_t tail = 0;
 };
 
 // lanes: lanes that hold adjoint checkpoints (0: one lane group per task);
 // cont_lanes: lanes of the FP64 continuation launch (0: none)
+// tail_rec: doubles per tail hand-off record (0: no hand-off)
 WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
                 bool grad, bool solve, size_t lanes = 0, size_t cont_lanes = 0,
-                int cont_npl = 0, int cont_K = 0) {
+                int cont_npl = 0, int cont_K = 0, int tail_rec = 0) {
   if (cont_npl == 0) cont_npl = s.npl;
   WsLayout L;
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
@@ -215,6 +219,10 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
     off += align_up(nck64 * 2 * cont_npl * cont_lanes * 8, 256);
     L.seg64 = off;
     off += align_up((size_t)K64 * 2 * cont_npl * cont_lanes * 8, 256);
+    if (tail_rec > 0) {
+      L.tail = off;
+      off += align_up(BG * (size_t)tail_rec * 8, 256);
+    }
   }
   L.total = off;
   return L;
@@ -561,6 +569,55 @@ int cont_shape_for(const Shape& s, int lpt, Shape& cs) {
                                    std::to_string(s.lpt) + " descent shape");
 }
 
+// The tail-continuation kernels by shape and speed profile.
+hipError_t dispatch_resume(const Shape& s, int mk, const hj::SolveArgs<double>& A,
+                           int64_t grid_groups, hipStream_t st) {
+#define HJ_CASE(NPL, LPT)                                                                 \
+  if (s.npl == NPL && s.lpt == LPT)                                                       \
+    return mk == HJ_M_TANH                                                                \
+               ? hj::launch_resume<hj::Cfg<double, NPL, LPT, HJ_M_TANH>>(A, grid_groups, st) \
+               : hj::launch_resume<hj::Cfg<double, NPL, LPT, HJ_M_RAT>>(A, grid_groups, st);
+  HJ_FOR_EACH_RESUME_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return hipErrorInvalidValue;
+}
+
+int64_t dispatch_resident_resume(const Shape& s, int mk) {
+#define HJ_CASE(NPL, LPT)                                                          \
+  if (s.npl == NPL && s.lpt == LPT)                                                \
+    return mk == HJ_M_TANH                                                         \
+               ? hj::resident_resume_groups<hj::Cfg<double, NPL, LPT, HJ_M_TANH>>() \
+               : hj::resident_resume_groups<hj::Cfg<double, NPL, LPT, HJ_M_RAT>>();
+  HJ_FOR_EACH_RESUME_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return 0;
+}
+
+bool has_resume(const Shape& s) {
+  bool found = false;
+#define HJ_CASE(NPL, LPT) \
+  if (!s.dr && s.npl == NPL && s.lpt == LPT) found = true;
+  HJ_FOR_EACH_RESUME_SHAPE(HJ_CASE)
+#undef HJ_CASE
+  return found;
+}
+
+// Whether a solve hands its slow slots to a tail continuation, and the
+// continuation's lane shape: the compiled shape with tail_lanes_per_task
+// lanes (default 2) and the descent shape's padded dimension.
+bool tail_active(const Shape& s, bool f64, const hj_opts* o) {
+  return f64 && o->tail_budget > 0 && o->mode == HJ_GD_ADJ && !s.dr;
+}
+int tail_lanes(const hj_opts* o) { return o->tail_lanes_per_task > 0 ? o->tail_lanes_per_task : 2; }
+int tail_shape_for(const Shape& s, const hj_opts* o, Shape& ts) {
+  if (!cont_shape_of(s, tail_lanes(o), ts) || !has_resume(ts))
+    return fail(HJ_EUNSUPPORTED, "no tail-continuation kernel with " +
+                                     std::to_string(tail_lanes(o)) + " lanes per task for the " +
+                                     std::to_string(s.npl) + "x" + std::to_string(s.lpt) +
+                                     " descent shape");
+  return HJ_OK;
+}
+
 // Lane groups of the FP64 continuation launch of an FP32 GD solve over ntask
 // slots (0: no continuation).
 int64_t continue_groups(const Shape& s, int mk, const hj_opts* o, int64_t ntask) {
@@ -610,12 +667,22 @@ WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nstep
   const int64_t ntask = B * (int64_t)G;
   *groups = schedule_groups<T>(s, mk, o->mode, o->schedule, ntask, o->max_groups);
   Shape cs{};
-  if (!cont_shape_of(s, o->cont_lanes_per_task, cs)) cs = s;  // rejected by the caller
-  *cgroups = continue_groups(cs, mk, o, ntask);
+  int tail_rec = 0;
+  if (tail_active(s, sizeof(T) == 8, o)) {
+    // the tail continuation takes the continuation's counters and checkpoints
+    if (!cont_shape_of(s, tail_lanes(o), cs) || !has_resume(cs)) cs = s;  // rejected by the caller
+    int64_t tg = has_resume(cs) ? dispatch_resident_resume(cs, mk) : 0;
+    if (o->max_groups > 0) tg = std::min<int64_t>(tg, o->max_groups);
+    *cgroups = std::max<int64_t>(1, std::min<int64_t>(tg, ntask));
+    tail_rec = hj::kTailHead + 2 * n;
+  } else {
+    if (!cont_shape_of(s, o->cont_lanes_per_task, cs)) cs = s;  // rejected by the caller
+    *cgroups = continue_groups(cs, mk, o, ntask);
+  }
   const size_t ck_lanes = *groups > 0 ? align_up((size_t)*groups * s.lpt, 256) : 0;
   const size_t cont_lanes = *cgroups > 0 ? align_up((size_t)*cgroups * cs.lpt, 256) : 0;
   return layout(s, n, B, G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes, cont_lanes,
-                cs.npl, eff_K(K, cs, true, nsteps));
+                cs.npl, eff_K(K, cs, true, nsteps), tail_rec);
 }
 
 template <typename T>
@@ -625,7 +692,15 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   Shape s{}, cs{};
   int rc = shape_for(H, n, o->lanes_per_task, sizeof(T) == 4, s);
   if (rc) return rc;
-  rc = cont_shape_for(s, o->cont_lanes_per_task, cs);
+  const bool tail = tail_active(s, sizeof(T) == 8, o);
+  if (tail) {
+    rc = tail_shape_for(s, o, cs);
+  } else {
+    if (o->tail_budget > 0)
+      return fail(HJ_EUNSUPPORTED, "tail hand-offs take the FP64 adjoint descent of a "
+                                   "problem without a drift matrix");
+    rc = cont_shape_for(s, o->cont_lanes_per_task, cs);
+  }
   if (rc) return rc;
   const int npad = s.npad();
   const int K = eff_K(o->ckpt_K, s, sizeof(T) == 8, nsteps);
@@ -694,17 +769,42 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   A.n_inst = 0;
   A.handoff = nullptr;
   A.handoff_n = nullptr;
+  A.tail_budget = 0;
+  A.tail_stride = 0;
+  A.tail = nullptr;
+  A.tail_n = nullptr;
   unsigned long long* ctr = nullptr;
   if (cgroups > 0) {
-    A.handoff = reinterpret_cast<int64_t*>(base + WL.handoff);
     ctr = reinterpret_cast<unsigned long long*>(base + WL.cont_ctr);
-    A.handoff_n = ctr;
+    if (tail) {
+      A.tail_budget = o->tail_budget;
+      A.tail_stride = hj::kTailHead + 2 * n;
+      A.tail = reinterpret_cast<double*>(base + WL.tail);
+      A.tail_n = ctr;
+    } else {
+      A.handoff = reinterpret_cast<int64_t*>(base + WL.handoff);
+      A.handoff_n = ctr;
+    }
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, ctr, 16);
     HJ_HIP(hipGetLastError());
   }
 
   if (o->ev_begin) HJ_HIP(hipEventRecord(static_cast<hipEvent_t>(o->ev_begin), st));
   HJ_HIP(dispatch_solve<T>(s, kernel_mk(H), A, o->mode, groups, st));
+  if constexpr (sizeof(T) == 8) {
+    if (tail && cgroups > 0) {
+      // the continuation: the same problem and records, its own lane shape,
+      // checkpoints and queue; no further hand-off
+      hj::SolveArgs<double> R = A;
+      R.tail_budget = 0;
+      R.K = eff_K(K, cs, true, nsteps);
+      R.ck = reinterpret_cast<double*>(base + WL.ck64);
+      R.seg = reinterpret_cast<double*>(base + WL.seg64);
+      R.stride = WL.stride64;
+      R.queue = ctr + 8;
+      HJ_HIP(dispatch_resume(cs, kernel_mk(H), R, cgroups, st));
+    }
+  }
   if constexpr (sizeof(T) == 4) {
     if (cgroups > 0) {
       hj::ContArgs<float> CA;
@@ -818,6 +918,8 @@ int check_opts(const hj_opts* o) {
     return fail(HJ_EINVAL, "bad schedule");
   if (o->max_groups < 0) return fail(HJ_EINVAL, "max_groups must be >= 0");
   if (o->cont_lanes_per_task < 0) return fail(HJ_EINVAL, "cont_lanes_per_task must be >= 0");
+  if (o->tail_budget < 0) return fail(HJ_EINVAL, "tail_budget must be >= 0");
+  if (o->tail_lanes_per_task < 0) return fail(HJ_EINVAL, "tail_lanes_per_task must be >= 0");
   if (o->n_group_cfg < 0 || (o->n_group_cfg > 0 && !o->group_cfg))
     return fail(HJ_EINVAL, "group_cfg must hold n_group_cfg entries");
   for (int c = 0; c < o->n_group_cfg; ++c) {
@@ -1209,6 +1311,10 @@ int plan_t(const hj_instance* inst, int n_inst, const hj_opts* o, hj_batch_plan_
     A.handoff = g.cgroups > 0 ? reinterpret_cast<int64_t*>(base + g.handoff) : nullptr;
     A.handoff_n =
         g.cgroups > 0 ? reinterpret_cast<unsigned long long*>(base + g.cont_ctr) : nullptr;
+    A.tail_budget = 0;
+    A.tail_stride = 0;
+    A.tail = nullptr;
+    A.tail_n = nullptr;
     args.push_back(A);
   }
   // capture the launch groups into a graph as parallel branches (fork from
@@ -1483,6 +1589,8 @@ int32_t hj_batch_plan(int32_t H_kind, int32_t J_kind, const hj_instance* inst, i
   int rc = check_opts(&o);
   if (rc) return rc;
   if (o.mode != HJ_GD_ADJ) return fail(HJ_EUNSUPPORTED, "batched solves use HJ_GD_ADJ");
+  if (o.tail_budget > 0)
+    return fail(HJ_EUNSUPPORTED, "tail hand-offs are for single solves, not batch plans");
   if (needs_paper(H_kind, J_kind, &o))
     return fail(HJ_EUNSUPPORTED, "batched plans take the quadratic family, ellipsoid data, "
                                  "the F1 / G functionals and RK4");

@@ -468,17 +468,83 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C0::T> A) {
 // ---------------------------------------------------------------------------
 // gradient descent with the exact discrete gradient (adjoint + checkpoints)
 // ---------------------------------------------------------------------------
-template <class C, bool MULTI>
+// Save (TAIL_SAVE) or restore the descent state of a slot in tail record r.
+template <class C>
+__device__ __forceinline__ void tail_save(const SolveArgs<double>& A, int sub, int64_t r,
+                                          int64_t task, int it, int att, double alpha,
+                                          double phi, double rho, const SlotBest& best,
+                                          const double (&v)[C::NPL], const double (&g)[C::NPL]) {
+  const int n = A.P.n;
+  double* rec = A.tail + r * A.tail_stride;
+  if (sub == 0) {
+    rec[0] = (double)task;
+    rec[1] = (double)it;
+    rec[2] = (double)att;
+    rec[3] = alpha;
+    rec[4] = phi;
+    rec[5] = rho;
+    rec[6] = best.phi;
+    rec[7] = best.rho;
+    rec[8] = (double)best.cert;
+    rec[9] = (double)best.status;
+    rec[10] = (double)best.iters;
+    rec[11] = (double)best.attempts;
+    rec[12] = (double)best.n_fwd;
+    rec[13] = (double)best.n_bwd;
+  }
+  store_row<C>(rec + kTailHead, n, sub, v);
+  store_row<C>(rec + kTailHead + n, n, sub, g);
+}
+template <class C>
+__device__ __forceinline__ int64_t tail_restore(const SolveArgs<double>& A, int sub, int64_t r,
+                                                int& it, int& att, double& alpha, double& phi,
+                                                double& rho, SlotBest& best,
+                                                double (&v)[C::NPL], double (&g)[C::NPL]) {
+  const int n = A.P.n;
+  const double* rec = A.tail + r * A.tail_stride;
+  it = (int)rec[1];
+  att = (int)rec[2];
+  alpha = rec[3];
+  phi = rec[4];
+  rho = rec[5];
+  best.phi = rec[6];
+  best.rho = rec[7];
+  best.cert = (int32_t)rec[8];
+  best.status = (int32_t)rec[9];
+  best.iters = (int32_t)rec[10];
+  best.attempts = (int32_t)rec[11];
+  best.n_fwd = (int64_t)rec[12];
+  best.n_bwd = (int64_t)rec[13];
+  load_row<C>(rec + kTailHead, n, sub, v);
+  load_row<C>(rec + kTailHead + n, n, sub, g);
+  return (int64_t)rec[0];
+}
+
+// RESUME: the continuation launch of a tail hand-off (FP64, one problem, no
+// drift): lane groups pop record indices and carry each slot on from its
+// saved state, exactly where the first launch left it.
+template <class C, bool MULTI, bool RESUME>
 __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
   constexpr int NPL = C::NPL;
   static_assert(!(MULTI && C::DR), "batched instances carry no drift");
+  static_assert(!RESUME || (sizeof(T) == 8 && !MULTI && !C::DR),
+                "tail hand-offs are FP64 single-problem descents without drift");
+  constexpr bool kTail = sizeof(T) == 8 && !MULTI && !C::DR;
   __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = C::sub_of(threadIdx.x);
-  int64_t task = C::task_of(lane);
-  // matrix-core kernels keep lanes without a task as idle wave members
-  int live = task < A.ntask ? 1 : 0;
+  int64_t task = 0, ridx = 0, rcount = 0;
+  int live;
+  if constexpr (RESUME) {
+    rcount = (int64_t)*A.tail_n;
+    ridx = pop_task<C>(A.queue, sub);
+    live = ridx < rcount ? 1 : 0;
+  } else {
+    task = C::task_of(lane);
+    // matrix-core kernels keep lanes without a task as idle wave members
+    live = task < A.ntask ? 1 : 0;
+  }
   if constexpr (!C::DR) {
     if (!live) return;
   }
@@ -489,16 +555,21 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
     tc.L.aop = s_aop;
     tc.L.set_dl(s_aop + C::kDriftTable);
   }
-  tc.bind(A, live != 0 ? task : 0, sub);
   T v[NPL], g[NPL];
-  load_row<C>(tc.g0, tc.P(A).n, sub, v);
-#pragma unroll
-  for (int k = 0; k < NPL; ++k) g[k] = T(0);
   SlotBest best;
-  best.reset();
   // it < 0 marks the first pass of an attempt (see k_solve_cd)
   int att = 0, it = -1;
   T alpha = A.alpha0, phi = T(0), rho = T(0);
+  if constexpr (RESUME) {
+    task = tail_restore<C>(A, sub, ridx, it, att, alpha, phi, rho, best, v, g);
+    tc.bind(A, task, sub);
+  } else {
+    tc.bind(A, live != 0 ? task : 0, sub);
+    load_row<C>(tc.g0, tc.P(A).n, sub, v);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) g[k] = T(0);
+    best.reset();
+  }
   while (true) {
     const bool start = it < 0;
     const Problem<T>& P = tc.P(A);
@@ -557,6 +628,23 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
       ++it;
       status = stop_status<C>(A, v, phi, smax, alpha, it);
     }
+    if constexpr (kTail && !RESUME) {
+      // tail hand-off: the slot is still descending after its budget of
+      // objective evaluations; its state goes to a record and the group
+      // takes the next task
+      if (A.tail_budget > 0 && status < 0 && best.n_fwd >= A.tail_budget) {
+        const int64_t r = pop_task<C>(A.tail_n, sub);
+        tail_save<C>(A, sub, r, task, it, att, alpha, phi, rho, best, v, g);
+        task = next_task<C>(A, sub);
+        if (task < 0) break;
+        tc.bind(A, task, sub);
+        best.reset();
+        att = 0;
+        load_row<C>(tc.g0, tc.P(A).n, sub, v);
+        it = -1;
+        continue;
+      }
+    }
     const bool ending = live != 0 && status >= 0;
     double phi64, rho64;
     attempt_values<C, MULTI>(A, tc, sub, v, phi, rho, status, ending, phi64, rho64);
@@ -569,6 +657,13 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
       if (done || handoff) {
         write_slot<C, MULTI>(A, tc, sub, task, best);
         if (handoff && sub == 0) A.handoff[atomicAdd(A.handoff_n, 1ULL)] = task;
+        if constexpr (RESUME) {
+          ridx = pop_task<C>(A.queue, sub);
+          if (ridx >= rcount) break;
+          task = tail_restore<C>(A, sub, ridx, it, att, alpha, phi, rho, best, v, g);
+          tc.bind(A, task, sub);
+          continue;
+        }
         task = next_task<C>(A, sub);
         att = 0;
         if (task < 0) {
@@ -910,7 +1005,7 @@ int64_t resident_groups(int mode) {
   if (mode == HJ_CD_FD)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_cd<C>, 256, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false, false>, 256, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return (int64_t)cus * per_cu * (256 / C::LPT);
 }
@@ -934,10 +1029,10 @@ hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, int64_t gri
     if constexpr (C::DR) {
       return hipErrorInvalidValue;  // batches carry no drift
     } else {
-      hipLaunchKernelGGL((k_solve_gd<C, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
+      hipLaunchKernelGGL((k_solve_gd<C, true, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
     }
   } else {
-    hipLaunchKernelGGL((k_solve_gd<C, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
+    hipLaunchKernelGGL((k_solve_gd<C, false, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
   }
   return hipGetLastError();
 }
@@ -972,6 +1067,30 @@ hipError_t launch_continue(const ContArgs<float>& A, bool multi, int64_t grid_gr
   } else {
     hipLaunchKernelGGL((k_continue_gd<C, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
   }
+  return hipGetLastError();
+}
+
+template <class C>
+int64_t resident_resume_groups() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false, true>, 256,
+                                                   0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (int64_t)cus * per_cu * (256 / C::LPT);
+}
+
+template <class C>
+hipError_t launch_resume(const SolveArgs<double>& A, int64_t grid_groups, hipStream_t st) {
+  const int block = 256;
+  const int64_t grid = (grid_groups * C::LPT + block - 1) / block;
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, st, A.queue, 0ULL);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve_gd<C, false, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
   return hipGetLastError();
 }
 
@@ -1044,6 +1163,14 @@ hipError_t launch_scatter_diag(const InstDesc<T>* inst, int n_inst, int64_t tota
   template hipError_t hj::launch_continue<hj::Cfg<double, NPL, LPT, MK, DR>>(              \
       const hj::ContArgs<float>&, bool, int64_t, hipStream_t);                              \
   template int64_t hj::resident_continue_groups<hj::Cfg<double, NPL, LPT, MK, DR>>();
+// The tail-continuation kernels of one FP64 lane shape.
+#define HJ_INSTANTIATE_RESUME_MK(NPL, LPT, MK)                                         \
+  template hipError_t hj::launch_resume<hj::Cfg<double, NPL, LPT, MK>>(                \
+      const hj::SolveArgs<double>&, int64_t, hipStream_t);                            \
+  template int64_t hj::resident_resume_groups<hj::Cfg<double, NPL, LPT, MK>>();
+#define HJ_INSTANTIATE_RESUME(NPL, LPT)            \
+  HJ_INSTANTIATE_RESUME_MK(NPL, LPT, HJ_M_TANH)    \
+  HJ_INSTANTIATE_RESUME_MK(NPL, LPT, HJ_M_RAT)
 #define HJ_INSTANTIATE_CONT(NPL, LPT)                     \
   HJ_INSTANTIATE_CONT_MK(NPL, LPT, HJ_M_TANH, false)      \
   HJ_INSTANTIATE_CONT_MK(NPL, LPT, HJ_M_RAT, false)

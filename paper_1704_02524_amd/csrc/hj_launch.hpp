@@ -65,7 +65,23 @@ template <typename T> struct SolveArgs {
   // its record written and its task index appended to `handoff`
   int64_t* handoff;                 // [ntask]
   unsigned long long* handoff_n;    // entries in handoff (starts at 0)
+  // FP64 single-problem adjoint descent with a tail hand-off (0 / null
+  // otherwise): a slot still descending after tail_budget objective
+  // evaluations leaves its whole descent state in a record of `tail`
+  // (kTailHead values, then v and g, tail_stride doubles per record; the
+  // record index from *tail_n, which starts at 0), and a second launch of a
+  // wider lane shape resumes it from there (RESUME: the records to resume
+  // are tail[0 .. *tail_n), handed out through `queue`, which starts at 0)
+  int tail_budget;
+  int tail_stride;
+  double* tail;
+  unsigned long long* tail_n;
 };
+
+// Head of a tail record: task, iteration, attempt, alpha, phi, rho, then
+// the slot's best attempt so far (phi, rho, cert, status, iterations,
+// attempts, forward and adjoint counts); v and g follow.
+constexpr int kTailHead = 14;
 
 // FP64 continuation of the slots an FP32 launch handed off: each resumes the
 // descent in FP64 from its FP32 result (then restarts in FP64 from its
@@ -149,6 +165,13 @@ hipError_t launch_continue(const ContArgs<float>& A, bool multi, int64_t grid_gr
                            hipStream_t st);
 template <class C>
 int64_t resident_continue_groups();
+// The continuation of a tail hand-off (FP64, one problem, no drift):
+// grid_groups lane groups of configuration C pop indices of A.tail's
+// *A.tail_n records from A.queue (reset to 0 by this call) and resume them.
+template <class C>
+hipError_t launch_resume(const SolveArgs<double>& A, int64_t grid_groups, hipStream_t st);
+template <class C>
+int64_t resident_resume_groups();
 template <typename T>
 hipError_t launch_select(int64_t B, int G, int n, int formula, const double* s_phi,
                          const int32_t* s_cert, const T* s_v, double* out_u, T* out_arg,
@@ -194,3 +217,6 @@ static_assert(4 * kDriftNpl[2] == HJ_MAX_N_DRIFT, "drift shapes cover HJ_MAX_N_D
   X(2, 1) X(4, 1) X(4, 2) X(5, 2) X(3, 4) X(4, 4) X(8, 4) X(8, 8) X(13, 8) X(16, 8) \
   X(2, 2) X(8, 1) X(2, 4) X(10, 1) X(8, 2) X(4, 8) X(7, 16)
 #define HJ_FOR_EACH_DRIFT_NPL(X) X(4) X(8) X(16)
+// FP64 shapes with a tail-continuation kernel (at most 4 lanes per task)
+#define HJ_FOR_EACH_RESUME_SHAPE(X) \
+  X(2, 1) X(4, 1) X(2, 2) X(8, 1) X(2, 4) X(4, 2) X(5, 2) X(10, 1) X(3, 4) X(4, 4) X(8, 2) X(8, 4)

@@ -52,7 +52,8 @@ class Opts(C.Structure):
                 ("max_groups", C.c_int32), ("fp64_continue", C.c_int32),
                 ("ode", C.c_int32), ("M", C.c_int32), ("momentum", C.c_double),
                 ("group_cfg", C.c_void_p), ("n_group_cfg", C.c_int32),
-                ("cont_lanes_per_task", C.c_int32)]
+                ("cont_lanes_per_task", C.c_int32), ("tail_budget", C.c_int32),
+                ("tail_lanes_per_task", C.c_int32)]
 
 
 class GroupCfg(C.Structure):
