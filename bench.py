@@ -135,12 +135,16 @@ def measured_traffic(workload, launch):
 
 
 def phase_record(wl, host, launch, workload):
-    """Executed instructions of the dominant kernel traced to its phases:
+    """Executed instructions of the dominant kernels traced to their phases:
     instructions per step of the forward, recompute and reverse loops (static
-    counts from the kernel's assembly, profiles/isa_phases_<workload>.md,
-    used only while the kernel-source digest matches) times the steps the
+    counts from the kernels' assembly, profiles/isa_phases_<workload>.md,
+    used only while the kernel-source digest matches) times the steps each
     launch executed in each phase (lane-steps, from the per-slot forward and
-    adjoint counts), beside each phase's algorithmic flops per step."""
+    adjoint counts), beside each phase's algorithmic flops per step.  With a
+    tail hand-off, a slot's first `tail_budget` evaluations ran in the
+    descent launch and the rest in the continuation (its adjoint sweeps
+    split in the same proportion, an estimate), on tail_lanes_per_task
+    lanes each."""
     path = os.path.join(ROOT, "profiles", f"isa_phases_{workload}.md")
     try:
         with open(path) as f:
@@ -151,23 +155,42 @@ def phase_record(wl, host, launch, workload):
         return None
     N, n = wl.nsteps, wl.n
     K = int(launch.get("ckpt_K", 0) or 0)
-    if K < 1 or e.get("lpt") != launch.get("lanes_per_task"):
+    budget = int(launch.get("tail_budget", 0) or 0)
+    ks = e["kernels"]
+    first = ks["handoff"] if budget > 0 else ks["descent"]
+    if K < 1 or first["lpt"] != launch.get("lanes_per_task"):
         return None
-    fwd, bwd = float(host["slot_fwd"].sum()), float(host["slot_bwd"].sum())
+    fwd = host["slot_fwd"].astype(float)
+    bwd = host["slot_bwd"].astype(float)
+    launches = [("descent", first, fwd, bwd, 1)]
+    if budget > 0:
+        tail = ks.get("tail")
+        if tail is None or tail["lpt"] != launch.get("tail_lanes_per_task"):
+            return None
+        f1 = np.minimum(fwd, budget)
+        b1 = bwd * np.where(fwd > 0, f1 / np.maximum(fwd, 1), 1.0)
+        launches = [("descent", first, f1, b1, 1), ("tail", tail, fwd - f1, bwd - b1, tail["lpt"])]
     step = 4 * (16 * n + 12) + 12
-    steps = {"forward": fwd * N, "recompute": bwd * (N - (N + K - 1) // K),
-             "reverse": bwd * N}
     alg = {"forward": step, "recompute": step, "reverse": 1.75 * step}
-    valu = {k: sum(e["phases"][k][c] for c in ("fp64", "agpr", "valu_other")) for k in steps}
-    lane_valu = {k: steps[k] * valu[k] for k in steps}
-    tot = sum(lane_valu.values())
-    out = {"source": "instructions per step from the kernel's assembly x lane-steps executed",
-           "launch_lane_valu": tot}
-    for k in steps:
-        out[k] = {"lane_steps": steps[k], "valu_per_step": valu[k],
-                  "fp64_per_step": e["phases"][k]["fp64"],
-                  "agpr_moves_per_step": e["phases"][k]["agpr"],
-                  "method_flops_per_step": alg[k], "valu_share": lane_valu[k] / tot}
+    out = {"source": "instructions per step from the kernels' assembly x lane-steps executed"}
+    tot = 0.0
+    for name, k, f, b, lanes in launches:
+        steps = {"forward": f.sum() * N, "recompute": b.sum() * (N - (N + K - 1) // K),
+                 "reverse": b.sum() * N}
+        rec = {"shape": f"{k['npl']}x{k['lpt']}"}
+        for ph in steps:
+            c = k["phases"][ph]
+            valu = c["fp64"] + c["agpr"] + c["valu_other"]
+            rec[ph] = {"lane_steps": steps[ph] * lanes, "valu_per_step": valu,
+                       "fp64_per_step": c["fp64"], "agpr_moves_per_step": c["agpr"],
+                       "method_flops_per_step": alg[ph]}
+            tot += steps[ph] * lanes * valu
+        out[name] = rec
+    for name, *_ in launches:
+        for ph in ("forward", "recompute", "reverse"):
+            r = out[name][ph]
+            r["valu_share"] = r["lane_steps"] * r["valu_per_step"] / tot
+    out["launch_lane_valu"] = tot
     return out
 
 
@@ -453,6 +476,10 @@ def measure_single(wl, workload, steps, warmup, cfg):
     wall, kern, host = run_gpu(wl, steps, warmup, mode_name, cfg)
     n_cert = int((host["cert"] == 1).sum())
     kernel = "k_solve_gd" if wl.mode == W.GD_ADJ else "k_solve_cd"
+    if cfg.get("tail_budget"):
+        kernel = (f"k_solve_gd with a tail hand-off after {cfg['tail_budget']} evaluations + "
+                  f"k_solve_gd continuation on {cfg.get('tail_lanes_per_task', 2)} lanes per "
+                  f"task (the interval between the events spans both launches)")
     return {
         "value": n_cert / wall, "unit": "certified solves/s", "ms_per_step": wall * 1e3,
         "dtype": "f64" if wl.dtype == W.F64 else "f32",

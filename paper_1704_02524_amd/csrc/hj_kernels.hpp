@@ -520,17 +520,21 @@ __device__ __forceinline__ int64_t tail_restore(const SolveArgs<double>& A, int 
   return (int64_t)rec[0];
 }
 
-// RESUME: the continuation launch of a tail hand-off (FP64, one problem, no
-// drift): lane groups pop record indices and carry each slot on from its
-// saved state, exactly where the first launch left it.
-template <class C, bool MULTI, bool RESUME>
+// TAIL (FP64, one problem, no drift): kTailOff, the plain descent;
+// kTailHandOff, a descent that hands slots over its evaluation budget to
+// records; kTailResume, the continuation launch: lane groups pop record
+// indices and carry each slot on from its saved state, exactly where the
+// first launch left it.  (The hand-off is a variant of its own so that the
+// plain descent keeps its register allocation.)
+enum { kTailOff = 0, kTailHandOff = 1, kTailResume = 2 };
+template <class C, bool MULTI, int TAIL>
 __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename C::T> A) {
   using T = typename C::T;
   constexpr int NPL = C::NPL;
   static_assert(!(MULTI && C::DR), "batched instances carry no drift");
-  static_assert(!RESUME || (sizeof(T) == 8 && !MULTI && !C::DR),
+  static_assert(TAIL == kTailOff || (sizeof(T) == 8 && !MULTI && !C::DR),
                 "tail hand-offs are FP64 single-problem descents without drift");
-  constexpr bool kTail = sizeof(T) == 8 && !MULTI && !C::DR;
+  constexpr bool RESUME = TAIL == kTailResume;
   __shared__ T s_aop[C::DR ? C::kDriftTable + 4 * NPL : 1];
   const size_t lane = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int sub = C::sub_of(threadIdx.x);
@@ -628,7 +632,7 @@ __global__ __launch_bounds__(256, C::kWaves) void k_solve_gd(SolveArgs<typename 
       ++it;
       status = stop_status<C>(A, v, phi, smax, alpha, it);
     }
-    if constexpr (kTail && !RESUME) {
+    if constexpr (TAIL == kTailHandOff) {
       // tail hand-off: the slot is still descending after its budget of
       // objective evaluations; its state goes to a record and the group
       // takes the next task
@@ -1005,7 +1009,7 @@ int64_t resident_groups(int mode) {
   if (mode == HJ_CD_FD)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_cd<C>, 256, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false, kTailOff>, 256, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return (int64_t)cus * per_cu * (256 / C::LPT);
 }
@@ -1029,10 +1033,18 @@ hipError_t launch_solve(const SolveArgs<typename C::T>& A, int mode, int64_t gri
     if constexpr (C::DR) {
       return hipErrorInvalidValue;  // batches carry no drift
     } else {
-      hipLaunchKernelGGL((k_solve_gd<C, true, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
+      hipLaunchKernelGGL((k_solve_gd<C, true, kTailOff>), dim3((unsigned)grid), dim3(block), 0, st, A);
+    }
+  } else if (A.tail_budget > 0) {
+    if constexpr (sizeof(typename C::T) == 8 && !C::DR) {
+      hipLaunchKernelGGL((k_solve_gd<C, false, kTailHandOff>), dim3((unsigned)grid), dim3(block),
+                         0, st, A);
+    } else {
+      return hipErrorInvalidValue;  // hand-offs are FP64 descents without drift
     }
   } else {
-    hipLaunchKernelGGL((k_solve_gd<C, false, false>), dim3((unsigned)grid), dim3(block), 0, st, A);
+    hipLaunchKernelGGL((k_solve_gd<C, false, kTailOff>), dim3((unsigned)grid), dim3(block), 0,
+                       st, A);
   }
   return hipGetLastError();
 }
@@ -1076,7 +1088,7 @@ int64_t resident_resume_groups() {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false, true>, 256,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_solve_gd<C, false, kTailResume>, 256,
                                                    0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -1090,7 +1102,7 @@ hipError_t launch_resume(const SolveArgs<double>& A, int64_t grid_groups, hipStr
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, st, A.queue, 0ULL);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_gd<C, false, true>), dim3((unsigned)grid), dim3(block), 0, st, A);
+  hipLaunchKernelGGL((k_solve_gd<C, false, kTailResume>), dim3((unsigned)grid), dim3(block), 0, st, A);
   return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@ longest pass.  Multiplied by the steps a launch executes per phase, they
 trace the executed instructions of the launch to its phases.
 
     python -m paper_1704_02524_amd.isa_phases --source hj_inst_f64_1.hip \
-        --npl 10 --lpt 1 --mk 2 [--markdown out.md]
+        --npl 10 --lpt 1 --mk 2 [--tail-source hj_inst_r64_1.hip --tail-npl 5 \
+        --tail-lpt 2] [--markdown out.md]
 """
 from __future__ import annotations
 
@@ -63,9 +64,11 @@ def assemble(source: str) -> str:
     return out
 
 
-def kernel_symbol(npl: int, lpt: int, mk: int) -> str:
-    """Mangled name of k_solve_gd for one instance, double, no drift."""
-    return (f"_ZN2hj10k_solve_gdINS_3CfgIdLi{npl}ELi{lpt}ELi{mk}ELb0ELb0EEELb0EEEv"
+def kernel_symbol(npl: int, lpt: int, mk: int, tail: int = 0) -> str:
+    """Mangled name of k_solve_gd for one instance, double, no drift: the
+    plain descent (tail 0), the descent with a tail hand-off (1) or the
+    continuation of the hand-off (2)."""
+    return (f"_ZN2hj10k_solve_gdINS_3CfgIdLi{npl}ELi{lpt}ELi{mk}ELb0ELb0EEELb0ELi{tail}EEEv"
             "NS_9SolveArgsINT_1TEEE")
 
 
@@ -143,32 +146,40 @@ def _subtree(h, children):
     return out
 
 
-def count(source: str, npl: int, lpt: int, mk: int) -> dict:
+def count(source: str, npl: int, lpt: int, mk: int, tail: int = 0) -> dict:
     asm = assemble(source)
-    blocks, loops = parse(asm, kernel_symbol(npl, lpt, mk))
+    blocks, loops = parse(asm, kernel_symbol(npl, lpt, mk, tail))
     ph = phases(blocks, loops)
     return {k: {c: int(v.get(c, 0)) for c in CLASSES} | {"total": int(sum(v.values()))}
             for k, v in ph.items()}
 
 
-def markdown(res: dict, args, digest: str) -> str:
-    cmd = (f"python -m paper_1704_02524_amd.isa_phases --source {args.source} --npl {args.npl} "
-           f"--lpt {args.lpt} --mk {args.mk} --markdown {args.markdown}")
+def _rows(res: dict):
     rows = ["| phase | " + " | ".join(CLASSES) + " | total |",
             "|---|" + "---|" * (len(CLASSES) + 1)]
     for k, v in res.items():
         rows.append(f"| {k} | " + " | ".join(str(v[c]) for c in CLASSES) + f" | {v['total']} |")
-    rec = {"source_digest": digest, "npl": args.npl, "lpt": args.lpt, "mk": args.mk, "phases": res}
+    return rows
+
+
+def markdown(kernels: dict, cmd: str, digest: str) -> str:
+    """kernels: name -> (npl, lpt, mk, counts)."""
+    body = []
+    for name, (npl, lpt, mk, res) in kernels.items():
+        body += [f"{name}: `k_solve_gd` FP64 {npl}x{lpt}", "", *_rows(res), ""]
+    rec = {"source_digest": digest,
+           "kernels": {name: {"npl": npl, "lpt": lpt, "mk": mk, "phases": res}
+                       for name, (npl, lpt, mk, res) in kernels.items()}}
     return "\n".join([
-        f"# Instructions per step of each phase: `k_solve_gd` FP64 {args.npl}x{args.lpt}",
+        "# Instructions per step of each phase of the adjoint descent kernels",
         "",
         "Static counts from the gfx950 assembly of the library's own build (wave instructions of one",
-        "pass of each phase's loop body, skippable blocks included).  Command (repository root):",
+        "pass of each phase's loop body, skippable blocks included): the plain descent, the descent",
+        "with a tail hand-off and the hand-off's continuation.  Command (repository root):",
         "",
         f"    {cmd}",
         "",
-        *rows,
-        "",
+        *body,
         "Machine-readable copy:",
         "",
         "```json",
@@ -183,14 +194,27 @@ def main():
     ap.add_argument("--npl", type=int, default=10)
     ap.add_argument("--lpt", type=int, default=1)
     ap.add_argument("--mk", type=int, default=2)
+    ap.add_argument("--tail-source", default="hj_inst_r64_1.hip")
+    ap.add_argument("--tail-npl", type=int, default=5)
+    ap.add_argument("--tail-lpt", type=int, default=2)
     ap.add_argument("--markdown")
     args = ap.parse_args()
-    res = count(args.source, args.npl, args.lpt, args.mk)
-    print(json.dumps(res, indent=1))
+    kernels = {"descent": (args.npl, args.lpt, args.mk,
+                           count(args.source, args.npl, args.lpt, args.mk))}
+    if args.tail_lpt > 0:
+        kernels["handoff"] = (args.npl, args.lpt, args.mk,
+                              count(args.source, args.npl, args.lpt, args.mk, 1))
+        kernels["tail"] = (args.tail_npl, args.tail_lpt, args.mk,
+                           count(args.tail_source, args.tail_npl, args.tail_lpt, args.mk, 2))
+    print(json.dumps({k: v[3] for k, v in kernels.items()}, indent=1))
     if args.markdown:
         import bench
+        cmd = (f"python -m paper_1704_02524_amd.isa_phases --source {args.source} "
+               f"--npl {args.npl} --lpt {args.lpt} --mk {args.mk} --tail-source "
+               f"{args.tail_source} --tail-npl {args.tail_npl} --tail-lpt {args.tail_lpt} "
+               f"--markdown {args.markdown}")
         with open(args.markdown, "w") as fh:
-            fh.write(markdown(res, args, bench.source_digest()))
+            fh.write(markdown(kernels, cmd, bench.source_digest()))
 
 
 if __name__ == "__main__":

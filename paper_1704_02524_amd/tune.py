@@ -168,13 +168,48 @@ def tune(wl, tune_iters: int = 20, use_cache: bool = True, verbose: bool = False
     near = [r for r in results if r[0] <= 1.015 * results[0][0]]
     near.sort(key=lambda r: (-r[1].get("ckpt_K", 0), r[1]["lanes_per_task"]))
     best = near[0][1]
-    table[key] = {"config": best, "ms": near[0][0],
-                  "all": [{"ms": ms, **c} for ms, c in results]}
+    tail = tune_tail(wl, best, verbose=verbose)
+    table[key] = {"config": {**best, **tail["config"]}, "ms": near[0][0],
+                  "all": [{"ms": ms, **c} for ms, c in results], "tail": tail}
+    best = table[key]["config"]
     try:
         _save(table)
     except OSError:
         pass
     return dict(best)
+
+
+def tune_tail(wl, cfg: dict, min_gain: float = 1.02, verbose: bool = False) -> dict:
+    """The tail hand-off of an FP64 adjoint descent without drift: the
+    evaluation budget after which a slot moves to the wider continuation
+    launch, and that launch's lanes per task.  Timed on the whole workload
+    (the hand-off pays only where slots run long, which a shortened probe
+    does not show); kept when it is min_gain faster than no hand-off."""
+    if wl.dtype != W.F64 or wl.mode != W.GD_ADJ or wl.A is not None:
+        return {"config": {}}
+    x, g = hj.device_inputs(wl)
+    base = time_config(wl, x, g, cfg, reps=2)
+    if base is None:
+        return {"config": {}}
+    runs = []
+    for frac in (0.4, 0.5, 0.6, 0.7, 0.8):
+        budget = max(1, int(round(frac * (wl.max_iter + 1))))
+        for tl in (2, 4):
+            c = {**cfg, "tail_budget": budget, "tail_lanes_per_task": tl}
+            ms = time_config(wl, x, g, c, reps=2)
+            if verbose:
+                print(f"[tune] tail {c}: {ms} ms (none: {base:.1f})", file=sys.stderr,
+                      flush=True)
+            if ms is not None:
+                runs.append((ms, budget, tl))
+    out = {"none_ms": base, "all": [{"ms": m, "tail_budget": b, "tail_lanes_per_task": t}
+                                    for m, b, t in runs], "config": {}}
+    if runs:
+        ms, budget, tl = min(runs)
+        if base / ms >= min_gain:
+            out["config"] = {"tail_budget": budget, "tail_lanes_per_task": tl}
+            out["ms"] = ms
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -47,11 +47,15 @@ def test_drift_n32_full_size_sampled(hj):
     _check(wl, res, [0, 31337, 65535] + list(np.where(cert != 1)[0][:2]))
 
 
-def test_hopf_n10_full_size_sampled(hj):
+@pytest.mark.parametrize("tail", [0, 100], ids=["one_launch", "tail_handoff"])
+def test_hopf_n10_full_size_sampled(hj, tail):
     """4096 points x 16 guesses on one lane per task with checkpoints every
-    16 steps, the launch the headline benchmark times."""
+    16 steps (4 in the LDS plan), alone and, as the headline benchmark times
+    it, with the slots still descending after 100 evaluations handed to a
+    two-lane continuation launch."""
     wl = W.c1_hopf_n10(B=4096)
-    res = hj.solve(wl, *hj.device_inputs(wl), lanes_per_task=1, ckpt_K=16)
+    res = hj.solve(wl, *hj.device_inputs(wl), lanes_per_task=1, ckpt_K=16, tail_budget=tail,
+                   tail_lanes_per_task=2 if tail else 0)
     torch.cuda.synchronize()
     cert = res["cert"].cpu().numpy()
     assert (cert == 1).mean() > 0.999

@@ -63,3 +63,4 @@ def test_loop_nest_is_split_into_the_three_phases(tmp_path):
 def test_kernel_symbol_names_the_single_instance_adjoint_descent():
     s = I.kernel_symbol(10, 1, 2)
     assert s.startswith("_ZN2hj10k_solve_gd") and "CfgIdLi10ELi1ELi2E" in s
+    assert "ELi0EEEv" in s and "ELi2EEEv" in I.kernel_symbol(5, 2, 2, 2)
