@@ -172,16 +172,18 @@ struct WsLayout {
   // continuation queue), FP64 checkpoints over stride64 lanes
   size_t handoff = 0, cont_ctr = 0, ck64 = 0, seg64 = 0, stride64 = 0;
   // FP64 tail hand-off: the records (the continuation uses cont_ctr and the
-  // ck64 / seg64 checkpoints above)
-  size_t tail = 0;
+  // ck64 / seg64 checkpoints above) and, for a continuation shape of another
+  // padded dimension, its own parameter rows
+  size_t tail = 0, params2 = 0;
 };
 
 // lanes: lanes that hold adjoint checkpoints (0: one lane group per task);
 // cont_lanes: lanes of the FP64 continuation launch (0: none)
-// tail_rec: doubles per tail hand-off record (0: no hand-off)
+// tail_rec: doubles per tail hand-off record (0: no hand-off); tail_npad:
+// padded dimension of the continuation's parameter rows (0: the descent's)
 WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, int mode, int K,
                 bool grad, bool solve, size_t lanes = 0, size_t cont_lanes = 0,
-                int cont_npl = 0, int cont_K = 0, int tail_rec = 0) {
+                int cont_npl = 0, int cont_K = 0, int tail_rec = 0, int tail_npad = 0) {
   if (cont_npl == 0) cont_npl = s.npl;
   WsLayout L;
   const size_t tsz = dtype == HJ_F32 ? 4 : 8;
@@ -222,6 +224,10 @@ WsLayout layout(const Shape& s, int n, int64_t B, int G, int nsteps, int dtype, 
     if (tail_rec > 0) {
       L.tail = off;
       off += align_up(BG * (size_t)tail_rec * 8, 256);
+    }
+    if (tail_npad > 0) {
+      L.params2 = off;
+      off += align_up((size_t)tail_npad * 3 * (8 + 8), 256);
     }
   }
   L.total = off;
@@ -603,14 +609,23 @@ bool has_resume(const Shape& s) {
 }
 
 // Whether a solve hands its slow slots to a tail continuation, and the
-// continuation's lane shape: the compiled shape with tail_lanes_per_task
-// lanes (default 2) and the descent shape's padded dimension.
+// continuation's lane shape: the descent's with as many lanes per task, else
+// the library's shape for n with tail_lanes_per_task lanes (default 2); a
+// shape of another padded dimension gets parameter rows of its own.
 bool tail_active(const Shape& s, bool f64, const hj_opts* o) {
   return f64 && o->tail_budget > 0 && o->mode == HJ_GD_ADJ && !s.dr;
 }
 int tail_lanes(const hj_opts* o) { return o->tail_lanes_per_task > 0 ? o->tail_lanes_per_task : 2; }
-int tail_shape_for(const Shape& s, const hj_opts* o, Shape& ts) {
-  if (!cont_shape_of(s, tail_lanes(o), ts) || !has_resume(ts))
+bool tail_shape_of(const Shape& s, int n, int lpt, Shape& ts) {
+  if (lpt == s.lpt) {
+    ts = s;
+  } else if (!pick_shape(n, lpt, false, false, ts)) {
+    return false;
+  }
+  return has_resume(ts);
+}
+int tail_shape_for(const Shape& s, int n, const hj_opts* o, Shape& ts) {
+  if (!tail_shape_of(s, n, tail_lanes(o), ts))
     return fail(HJ_EUNSUPPORTED, "no tail-continuation kernel with " +
                                      std::to_string(tail_lanes(o)) + " lanes per task for the " +
                                      std::to_string(s.npl) + "x" + std::to_string(s.lpt) +
@@ -668,13 +683,15 @@ WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nstep
   *groups = schedule_groups<T>(s, mk, o->mode, o->schedule, ntask, o->max_groups);
   Shape cs{};
   int tail_rec = 0;
+  int tail_npad = 0;
   if (tail_active(s, sizeof(T) == 8, o)) {
     // the tail continuation takes the continuation's counters and checkpoints
-    if (!cont_shape_of(s, tail_lanes(o), cs) || !has_resume(cs)) cs = s;  // rejected by the caller
+    if (!tail_shape_of(s, n, tail_lanes(o), cs)) cs = s;  // rejected by the caller
     int64_t tg = has_resume(cs) ? dispatch_resident_resume(cs, mk) : 0;
     if (o->max_groups > 0) tg = std::min<int64_t>(tg, o->max_groups);
     *cgroups = std::max<int64_t>(1, std::min<int64_t>(tg, ntask));
     tail_rec = hj::kTailHead + 2 * n;
+    if (cs.npad() != s.npad()) tail_npad = cs.npad();
   } else {
     if (!cont_shape_of(s, o->cont_lanes_per_task, cs)) cs = s;  // rejected by the caller
     *cgroups = continue_groups(cs, mk, o, ntask);
@@ -682,7 +699,7 @@ WsLayout solve_layout(const Shape& s, int mk, int n, int64_t B, int G, int nstep
   const size_t ck_lanes = *groups > 0 ? align_up((size_t)*groups * s.lpt, 256) : 0;
   const size_t cont_lanes = *cgroups > 0 ? align_up((size_t)*cgroups * cs.lpt, 256) : 0;
   return layout(s, n, B, G, nsteps, o->dtype, o->mode, K, false, true, ck_lanes, cont_lanes,
-                cs.npl, eff_K(K, cs, true, nsteps), tail_rec);
+                cs.npl, eff_K(K, cs, true, nsteps), tail_rec, tail_npad);
 }
 
 template <typename T>
@@ -694,7 +711,7 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
   if (rc) return rc;
   const bool tail = tail_active(s, sizeof(T) == 8, o);
   if (tail) {
-    rc = tail_shape_for(s, o, cs);
+    rc = tail_shape_for(s, n, o, cs);
   } else {
     if (o->tail_budget > 0)
       return fail(HJ_EUNSUPPORTED, "tail hand-offs take the FP64 adjoint descent of a "
@@ -796,6 +813,13 @@ int solve_t(const hj_h_params* H, const hj_j_params* J, const void* x, int64_t B
       // the continuation: the same problem and records, its own lane shape,
       // checkpoints and queue; no further hand-off
       hj::SolveArgs<double> R = A;
+      if (cs.npad() != s.npad()) {
+        const double *d2 = nullptr, *dd2 = nullptr, *a2 = nullptr, *ad2 = nullptr;
+        rc = stage_params<double>(H, J, n, cs, base + WL.params2, st, &d2, &dd2, &a2, &ad2);
+        if (rc) return rc;
+        R.P = make_problem<double>(H, J, n, t, nsteps, o->formula, o->quad, dd2, cs.npad());
+        R.P64 = R.P;
+      }
       R.tail_budget = 0;
       R.K = eff_K(K, cs, true, nsteps);
       R.ck = reinterpret_cast<double*>(base + WL.ck64);

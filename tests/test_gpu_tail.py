@@ -56,11 +56,12 @@ def test_tail_with_the_same_shape_is_bitwise(hj, budget, schedule):
             assert (a["slot_attempts"] >= 1).all()
 
 
-@pytest.mark.parametrize("tail_lpt", [2])
+@pytest.mark.parametrize("tail_lpt", [2, 4])
 def test_tail_with_a_wider_shape_matches_the_reference(hj, tail_lpt):
-    """Hand-off to two lanes per task: equal certificates and u within 1e-9
-    of the single launch and of the reference (sampled points, every slot of
-    them recomputed)."""
+    """Hand-off to two lanes per task (the descent's padded dimension) and to
+    four (a padded dimension of its own, 12, with parameter rows of its own):
+    equal certificates and u within 1e-9 of the single launch and of the
+    reference (sampled points, every slot of them recomputed)."""
     wl = W.c1_hopf_n10(B=256)
     x, g = hj.device_inputs(wl)
     a = _host(hj.solve(wl, x, g, lanes_per_task=1, ckpt_K=4))
@@ -94,7 +95,7 @@ def test_tail_errors_are_reported(hj):
     wl = W.c1_hopf_n10(B=8)
     x, g = hj.device_inputs(wl)
     with pytest.raises(hj.HJError, match="tail-continuation kernel"):
-        hj.solve(wl, x, g, lanes_per_task=1, tail_budget=10, tail_lanes_per_task=8)
+        hj.solve(wl, x, g, lanes_per_task=1, tail_budget=10, tail_lanes_per_task=16)
     w32 = W._as_dtype(wl) if hasattr(W, "_as_dtype") else wl.with_(dtype=W.F32)
     with pytest.raises(hj.HJError, match="tail hand-offs"):
         hj.solve(w32, *hj.device_inputs(w32), tail_budget=10)
