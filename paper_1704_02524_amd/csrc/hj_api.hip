@@ -1029,6 +1029,9 @@ int paper_solve(int H_kind, const hj_h_params* H, int J_kind, const hj_j_params*
                 const hj_slot_diag* diag) {
   int rc = check_paper(H_kind, H, J_kind, n, o, true);
   if (rc) return rc;
+  if (o->tail_budget > 0)
+    return fail(HJ_EUNSUPPORTED, "tail hand-offs take the FP64 adjoint descent of a "
+                                 "problem without a drift matrix");
   const size_t BG = (size_t)B * gs->G;
   const size_t need = align_up(BG * (8 + 8 + 4 * 4 + 8 + 8), 256) + align_up(BG * n * 8, 256);
   void* ws = nullptr;

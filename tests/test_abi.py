@@ -153,3 +153,33 @@ def test_device_code_keeps_fp32_arithmetic_in_fp32():
         helper = code.find("__device__ __forceinline__ double fmaT(")
         # the only bare use is inside the double overload of the helper
         assert all(0 <= helper < u < helper + 200 for u in uses), (name, len(uses))
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the C structs have the header's sizes and field
+    offsets (a field added on one side only would shift every later one)."""
+    import ctypes
+    import subprocess
+    from paper_1704_02524_amd import hj
+    checks = {"hj_opts": (hj.Opts, ["dtype", "stream", "momentum", "group_cfg",
+                                    "cont_lanes_per_task", "tail_budget",
+                                    "tail_lanes_per_task"]),
+              "hj_group_cfg": (hj.GroupCfg, ["n_max", "cont_lanes_per_task"])}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "hj.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        src.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fields:
+            src.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src += ["  return 0;", "}"]
+    c = tmp_path / "sizes.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "sizes"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.check_call(["gcc", "-std=c11", "-I" + os.path.join(root, "include"), str(c),
+                           "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).split("\n")
+               if line)
+    for cname, (cls, fields) in checks.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in fields:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, f"{cname}.{f}"

@@ -101,3 +101,9 @@ def test_tail_errors_are_reported(hj):
         hj.solve(w32, *hj.device_inputs(w32), tail_budget=10)
     with pytest.raises(hj.HJError, match="tail_budget"):
         hj.solve(wl, x, g, tail_budget=-1)
+    wp = W.paper_ex2(-1, grid=2)
+    with pytest.raises(hj.HJError, match="tail hand-offs"):
+        hj.solve(wp, *hj.device_inputs(wp), tail_budget=10)
+    wd = W.c3_drift_n32(B=4)
+    with pytest.raises(hj.HJError, match="tail hand-offs"):
+        hj.solve(wd, *hj.device_inputs(wd), tail_budget=10)
