@@ -113,15 +113,21 @@ def parse(asm_path: str, symbol: str):
     return blocks, loops
 
 
-def phases(blocks, loops):
-    """The forward, recompute and reverse loops of the descent kernel."""
+def phases(blocks, loops, tanh_steps: bool = False):
+    """The forward, recompute and reverse loops of the descent kernel.  With
+    tanh_steps (the tanh speed profile: four FP64 tanh per RK4 step in every
+    phase, each with one hardware reciprocal), a loop body holding k x 4
+    reciprocals is taken as k steps unrolled, and its counts are divided by
+    k ("steps_per_pass" records k)."""
     own = collections.defaultdict(collections.Counter)
+    rcp = collections.Counter()
     order = []
     for b in blocks:
         if b["loop"]:
             if b["loop"] not in order:
                 order.append(b["loop"])
             own[b["loop"]].update(op_class(op) for op in b["ops"])
+            rcp[b["loop"]] += sum(op.startswith("v_rcp_f64") for op in b["ops"])
     children = collections.defaultdict(list)
     for h, info in loops.items():
         if info["parent"]:
@@ -136,7 +142,13 @@ def phases(blocks, loops):
         raise RuntimeError("unexpected loop nest: %s" % {h: loops[h] for h in loops})
     fwd = max(leaf, key=lambda h: own[h]["fp64"])
     rec, rev = [h for h in order if h in children[seg[0]]][:2]
-    return {"forward": own[fwd], "recompute": own[rec], "reverse": own[rev]}
+    out = {}
+    for name, h in (("forward", fwd), ("recompute", rec), ("reverse", rev)):
+        k = max(1, round(rcp[h] / 4)) if tanh_steps else 1
+        c = collections.Counter({key: v / k for key, v in own[h].items()})
+        c["steps_per_pass"] = k
+        out[name] = c
+    return out
 
 
 def _subtree(h, children):
@@ -149,16 +161,19 @@ def _subtree(h, children):
 def count(source: str, npl: int, lpt: int, mk: int, tail: int = 0) -> dict:
     asm = assemble(source)
     blocks, loops = parse(asm, kernel_symbol(npl, lpt, mk, tail))
-    ph = phases(blocks, loops)
-    return {k: {c: int(v.get(c, 0)) for c in CLASSES} | {"total": int(sum(v.values()))}
+    ph = phases(blocks, loops, tanh_steps=(mk == 2))
+    return {k: {c: round(v.get(c, 0)) for c in CLASSES}
+            | {"total": round(sum(v.get(c, 0) for c in CLASSES)),
+               "steps_per_pass": int(v["steps_per_pass"])}
             for k, v in ph.items()}
 
 
 def _rows(res: dict):
-    rows = ["| phase | " + " | ".join(CLASSES) + " | total |",
-            "|---|" + "---|" * (len(CLASSES) + 1)]
+    rows = ["| phase | " + " | ".join(CLASSES) + " | total | steps per loop pass |",
+            "|---|" + "---|" * (len(CLASSES) + 2)]
     for k, v in res.items():
-        rows.append(f"| {k} | " + " | ".join(str(v[c]) for c in CLASSES) + f" | {v['total']} |")
+        rows.append(f"| {k} | " + " | ".join(str(v[c]) for c in CLASSES) +
+                    f" | {v['total']} | {v['steps_per_pass']} |")
     return rows
 
 
@@ -173,9 +188,10 @@ def markdown(kernels: dict, cmd: str, digest: str) -> str:
     return "\n".join([
         "# Instructions per step of each phase of the adjoint descent kernels",
         "",
-        "Static counts from the gfx950 assembly of the library's own build (wave instructions of one",
-        "pass of each phase's loop body, skippable blocks included): the plain descent, the descent",
-        "with a tail hand-off and the hand-off's continuation.  Command (repository root):",
+        "Static counts from the gfx950 assembly of the library's own build (wave instructions per RK4",
+        "step of each phase's loop body, skippable blocks included; a body the compiler unrolled over",
+        "k steps is divided by k): the plain descent, the descent with a tail hand-off and the",
+        "hand-off's continuation.  Command (repository root):",
         "",
         f"    {cmd}",
         "",

@@ -55,9 +55,22 @@ def test_loop_nest_is_split_into_the_three_phases(tmp_path):
     blocks, loops = I.parse(str(p), "fn")
     assert loops["BB0_4"]["parent"] == "BB0_3" and loops["BB0_3"]["parent"] == "BB0_1"
     ph = I.phases(blocks, loops)
-    assert ph["forward"] == {"fp64": 2, "global": 1, "salu": 1}
-    assert ph["recompute"] == {"fp64": 1, "lds": 1, "salu": 1}
-    assert ph["reverse"] == {"agpr": 1, "fp64": 3, "valu_other": 1, "salu": 1}
+    assert ph["forward"] == {"fp64": 2, "global": 1, "salu": 1, "steps_per_pass": 1}
+    assert ph["recompute"] == {"fp64": 1, "lds": 1, "salu": 1, "steps_per_pass": 1}
+    assert ph["reverse"] == {"agpr": 1, "fp64": 3, "valu_other": 1, "salu": 1,
+                             "steps_per_pass": 1}
+
+
+def test_unrolled_loop_bodies_are_counted_per_step(tmp_path):
+    """Eight hardware reciprocals (two steps of four tanh) in the forward
+    loop: its counts are halved."""
+    rcp = "\tv_rcp_f64_e32 v[0:1], v[2:3]\n"
+    p = tmp_path / "k.s"
+    p.write_text(ASM.replace("\tglobal_store_dwordx2", rcp * 8 + "\tglobal_store_dwordx2"))
+    blocks, loops = I.parse(str(p), "fn")
+    ph = I.phases(blocks, loops, tanh_steps=True)
+    assert ph["forward"]["steps_per_pass"] == 2
+    assert ph["forward"]["fp64"] == (2 + 8) / 2
 
 
 def test_kernel_symbol_names_the_single_instance_adjoint_descent():
