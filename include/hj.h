@@ -205,9 +205,12 @@ typedef struct {
      * runs on wider lane groups instead of holding a one-lane wave for the
      * whole launch.  Results equal those without the hand-off up to the
      * rounding of the wider shape's sums (bit for bit with the descent's own
-     * lanes per task).  The tail shape must have the descent shape's padded
-     * dimension and at most 4 lanes per task; HJ_EUNSUPPORTED otherwise, for
-     * FP32, other descent modes, drift and batch plans. */
+     * lanes per task).  The continuation takes the library's shape for n
+     * with that many lanes (its own parameter rows where its padded
+     * dimension differs); shapes of more than 4 lanes per task, FP32, other
+     * descent modes, drift and batch plans are HJ_EUNSUPPORTED.  Adds
+     * (14 + 2n) x 8 bytes per slot and the continuation's checkpoints to the
+     * workspace. */
     int32_t tail_budget;
     int32_t tail_lanes_per_task;
 } hj_opts;

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(256) void k_solve_cd(SolveArgs<typename C0::T> A) {
 // ---------------------------------------------------------------------------
 // gradient descent with the exact discrete gradient (adjoint + checkpoints)
 // ---------------------------------------------------------------------------
-// Save (TAIL_SAVE) or restore the descent state of a slot in tail record r.
+// Save or restore the descent state of a slot in tail record r.
 template <class C>
 __device__ __forceinline__ void tail_save(const SolveArgs<double>& A, int sub, int64_t r,
                                           int64_t task, int it, int att, double alpha,
