@@ -107,3 +107,15 @@ def test_tail_errors_are_reported(hj):
     wd = W.c3_drift_n32(B=4)
     with pytest.raises(hj.HJError, match="tail hand-offs"):
         hj.solve(wd, *hj.device_inputs(wd), tail_budget=10)
+
+
+def test_tail_in_the_fixed_scratch_of_the_noalloc_entry(hj):
+    """hj_solve_noalloc with a hand-off gives hj_solve's results: the records
+    and the continuation's checkpoints fit the fixed scratch."""
+    wl = W.c1_hopf_n10(B=128)
+    x, g = hj.device_inputs(wl)
+    cfg = dict(lanes_per_task=1, ckpt_K=4, tail_budget=40, tail_lanes_per_task=2)
+    a = _host(hj.solve(wl, x, g, **cfg))
+    b = _host(hj.solve(wl, x, g, noalloc=True, **cfg))
+    for k in a:
+        np.testing.assert_array_equal(np.nan_to_num(a[k]), np.nan_to_num(b[k]), err_msg=k)
