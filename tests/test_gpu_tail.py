@@ -119,3 +119,24 @@ def test_tail_in_the_fixed_scratch_of_the_noalloc_entry(hj):
     b = _host(hj.solve(wl, x, g, noalloc=True, **cfg))
     for k in a:
         np.testing.assert_array_equal(np.nan_to_num(a[k]), np.nan_to_num(b[k]), err_msg=k)
+
+
+@pytest.mark.parametrize("n,lpt,tail_lpt", [(10, 2, 4), (7, 1, 2), (7, 1, 4), (3, 1, 2)])
+def test_tail_on_other_shapes(hj, n, lpt, tail_lpt):
+    """Other descent and continuation shapes, ragged dimensions (n = 7 and 3
+    pad to 8 and 4 components): equal certificates and u within 1e-9 of the
+    single launch."""
+    base = W.c1_hopf_n10(B=96)
+    rng = np.random.default_rng(n)
+    wl = base.with_(n=n, d=base.d[:n].copy(), a=base.a[:n].copy(),
+                    x=np.ascontiguousarray(base.x[:, :n]),
+                    guesses=np.ascontiguousarray(base.guesses[..., :n]),
+                    s=float(n))
+    x, g = hj.device_inputs(wl)
+    a = _host(hj.solve(wl, x, g, lanes_per_task=lpt))
+    b = _host(hj.solve(wl, x, g, lanes_per_task=lpt, tail_budget=45,
+                       tail_lanes_per_task=tail_lpt))
+    assert (a["slot_fwd"] > 45).any()
+    np.testing.assert_array_equal(a["cert"], b["cert"])
+    fin = np.isfinite(a["u"])
+    assert (np.abs(a["u"][fin] - b["u"][fin]) <= 1e-9 * np.maximum(1, np.abs(a["u"][fin]))).all()
