@@ -15,7 +15,7 @@
  *    each Euler step starts from: h sum_{k=0}^{N-1} iota(y_k);
  *  - Algorithm 1 is read literally: one coordinate update per k, no
  *    acceptance test, alpha halved every M updates, stop once d consecutive
- *    updates moved less than epsilon (steps 3-5), with a cap of max_iter
+ *    updates moved less than epsilon, with a cap of max_iter
  *    sweeps as a safety net the paper does not need;
  *  - for degree-1 homogeneous H the scale of p is free (H_p does not depend
  *    on it), so the certificate p(0) in dg(gamma(0)) of section 4.3 is
