@@ -62,7 +62,7 @@ def test_algorithm1_first_update_by_hand():
 
 
 def test_alpha_halves_every_M_updates():
-    """Algorithm 1's step 3: alpha halves after every M coordinate updates
+    """Algorithm 1's step-size rule: alpha halves after every M coordinate updates
     and never otherwise (no acceptance test).  The run is followed update by
     update in Python on the reference's own objective, with M = 2 over five
     updates (alpha, alpha, alpha/2, alpha/2, alpha/4)."""
