@@ -205,7 +205,11 @@ def tune_tail(wl, cfg: dict, min_gain: float = 1.02, verbose: bool = False) -> d
     out = {"none_ms": base, "all": [{"ms": m, "tail_budget": b, "tail_lanes_per_task": t}
                                     for m, b, t in runs], "config": {}}
     if runs:
-        ms, budget, tl = min(runs)
+        # near-ties (within 1.5 %, a probe's run-to-run spread) go to the
+        # larger budget (fewer slots moved), then to fewer lanes per task
+        best_ms = min(r[0] for r in runs)
+        near = [r for r in runs if r[0] <= 1.015 * best_ms]
+        ms, budget, tl = sorted(near, key=lambda r: (-r[1], r[2]))[0]
         if base / ms >= min_gain:
             out["config"] = {"tail_budget": budget, "tail_lanes_per_task": tl}
             out["ms"] = ms
