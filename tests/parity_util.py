@@ -13,7 +13,22 @@ from paper_1704_02524_amd import workloads as W
 
 def reference_point(wl, b):
     sub = wl.subset(b, b + 1)
+    return _solve_one(sub)
+
+
+def _solve_one(sub):
     return Oracle.from_workload(sub).solve(sub.x, sub.guesses, Oracle.opts_from_workload(sub))
+
+
+def reference_points(wl, points, workers=8):
+    """The reference at several points, in worker processes started fresh
+    (spawn: they load only the CPU reference, never the GPU runtime)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    subs = [wl.subset(int(b), int(b) + 1) for b in points]
+    with cf.ProcessPoolExecutor(max_workers=min(workers, len(subs)),
+                                mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_solve_one, subs))
 
 
 def in_band(ref, tol):

@@ -13,7 +13,7 @@ import torch
 from oracle.oracle import build as build_oracle
 from paper_1704_02524_amd import workloads as W
 
-from parity_util import check_point, tolerances
+from parity_util import check_point, reference_points, tolerances
 
 pytestmark = pytest.mark.gpu
 
@@ -28,11 +28,19 @@ def hj():
     return _hj
 
 
-def _check(wl, res, points, band=None):
+def _check(wl, res, points, band=None, random=0, seed=0):
+    """The given points and `random` more drawn uniformly, recomputed by the
+    reference in parallel worker processes."""
     u, cert, arg = (res[k].cpu().numpy() for k in ("u", "cert", "argopt"))
     tu, ta = tolerances(wl)
-    for b in points:
-        check_point(wl, int(b), u[b], cert[b], arg[b], tu, ta, band)
+    pts = list(dict.fromkeys(int(b) for b in points))
+    if random:
+        rng = np.random.default_rng(seed)
+        pts += [int(b) for b in rng.choice(wl.B, random, replace=False) if int(b) not in pts]
+    refs = reference_points(wl, pts) if len(pts) > 2 else [None] * len(pts)
+    for b, ref in zip(pts, refs):
+        check_point(wl, b, u[b], cert[b], arg[b], tu, ta, band, ref=ref)
+    print(f"{wl.name}: {len(pts)} points checked against the reference")
     return u, cert, arg
 
 
@@ -44,7 +52,7 @@ def test_drift_n32_full_size_sampled(hj):
     torch.cuda.synchronize()
     cert = res["cert"].cpu().numpy()
     assert (cert == 1).mean() > 0.999
-    _check(wl, res, [0, 31337, 65535] + list(np.where(cert != 1)[0][:2]))
+    _check(wl, res, [0, 31337, 65535] + list(np.where(cert != 1)[0][:2]), random=24, seed=1)
 
 
 @pytest.mark.parametrize("tail", [0, 100], ids=["one_launch", "tail_handoff"])
@@ -59,7 +67,8 @@ def test_hopf_n10_full_size_sampled(hj, tail):
     torch.cuda.synchronize()
     cert = res["cert"].cpu().numpy()
     assert (cert == 1).mean() > 0.999
-    _check(wl, res, [0, 1111, 2048, 4095] + list(np.where(cert != 1)[0][:2]))
+    _check(wl, res, [0, 1111, 2048, 4095] + list(np.where(cert != 1)[0][:2]), random=40,
+           seed=2)
 
 
 def test_hopf_n10_central_fd_full_size_sampled(hj):
@@ -71,7 +80,7 @@ def test_hopf_n10_central_fd_full_size_sampled(hj):
     torch.cuda.synchronize()
     cert = res["cert"].cpu().numpy()
     assert (cert == 1).mean() > 0.999
-    _check(wl, res, [0, 2048, 4095] + list(np.where(cert != 1)[0][:3]))
+    _check(wl, res, [0, 2048, 4095] + list(np.where(cert != 1)[0][:3]), random=16, seed=3)
 
 
 def test_lax_n100_fp32_full_size_sampled(hj):
@@ -83,14 +92,16 @@ def test_lax_n100_fp32_full_size_sampled(hj):
     torch.cuda.synchronize()
     cert = res["cert"].cpu().numpy()
     assert (cert == 1).mean() > 0.999
-    _check(wl, res, [0, 123457, 262143] + list(np.where(cert != 1)[0][:2]))
+    _check(wl, res, [0, 123457, 262143] + list(np.where(cert != 1)[0][:2]), random=64,
+           seed=4)
 
 
 @pytest.mark.parametrize("dtype", [W.F64, W.F32])
 def test_batched_full_size_sampled(hj, dtype):
-    """All 64 instances in one captured plan; two points of each of eight
-    instances (different n, t, N) and up to eight uncertified points against
-    the reference, certificate flags compared per point in both dtypes."""
+    """All 64 instances in one captured plan; three points (the first, the
+    last, one drawn) of each of sixteen instances (different n, t, N) and up
+    to eight uncertified points against the reference, certificate flags
+    compared per point in both dtypes."""
     wls = W.c2_batched(dtype=dtype)
     plan = hj.BatchPlan(wls)
     outs = plan.run()
@@ -101,8 +112,13 @@ def test_batched_full_size_sampled(hj, dtype):
     band = []
     unc = [(i, int(b)) for i, o in enumerate(outs)
            for b in np.where(o["cert"].cpu().numpy() != 1)[0]][:8]
-    picks = [(i, b) for i in range(0, 64, 8) for b in (0, wls[i].B - 1)] + unc
-    for i, b in picks:
-        _check(wls[i], outs[i], [b], band)
+    rng = np.random.default_rng(5)
+    picks = {}
+    for i in range(0, 64, 4):
+        picks.setdefault(i, []).extend([0, wls[i].B - 1, int(rng.integers(wls[i].B))])
+    for i, b in unc:
+        picks.setdefault(i, []).append(b)
+    for i, pts in picks.items():
+        _check(wls[i], outs[i], pts, band)
     assert len(band) <= 2, band
     plan.free()
