@@ -7,9 +7,10 @@ changes nothing (the recomputed segments are bit-identical to the forward
 solve).  For a single workload the tuner times every lane shape at the
 workload's own checkpoint interval on the full point set with the
 iteration cap lowered (so occupancy and per-iteration cost are those of the
-real run), keeps the fastest, and caches the choice in a JSON table keyed
-by the workload's shape.  For a batch it searches a per-class table on the
-whole plan (tune_batched).
+real run), keeps the fastest, then (FP64 adjoint descent without drift)
+times tail hand-off budgets on the whole workload (tune_tail), and caches
+the choice in a JSON table keyed by the workload's shape.  For a batch it
+searches a per-class table on the whole plan (tune_batched).
 """
 from __future__ import annotations
 
